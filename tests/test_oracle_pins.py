@@ -1,0 +1,532 @@
+"""Pins of the FP64 oracle to facts fixed outside it (no GPU needed).
+
+Each test names the passage of the paper it checks.  The independent sides are
+SciPy's Bernstein polynomials, exact rational closed forms, a null-space QP
+solve of objectives written row by row from the equations (tests/paper_ref.py),
+brute-force grids for the closed-form projections, and exact invariants.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2109_13030_amd import inputs
+from tests.paper_ref import PaperProblem, atan2z, bernstein_scipy
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny_problem(m=2, n=2, q=12, nv=8, flags=0, dynamic=True, seed=5, a_eq_b=False, rc=0.2):
+    """Small problem with active constraints (tight v/a limits)."""
+    rng = np.random.default_rng(seed)
+    tf = 6.0
+    t = np.arange(q) * tf / (q - 1)
+    r = (np.arange(m) - (m - 1) / 2) * 0.5
+    oa = rng.uniform(0.3, 0.8, n)
+    ob = oa.copy() if a_eq_b else rng.uniform(0.3, 0.8, n)
+    cx, cy = rng.uniform(3, 7, n), rng.uniform(3, 7, n)
+    vx, vy = (rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n)) if dynamic else (np.zeros(n), np.zeros(n))
+    ox = cx[:, None] + vx[:, None] * (t - tf / 2)
+    oy = cy[:, None] + vy[:, None] * (t - tf / 2)
+    return dict(q=q, nv=nv, tf=tf, r=r, ox=ox, oy=oy, oa=oa, ob=ob, rc=rc,
+                bx=np.array([1.0, 0.1, 0.0, 9.0, 0.0, 0.05]),
+                by=np.array([1.5, 0.0, 0.02, 8.0, -0.1, 0.0]),
+                bpsi=np.array([0.1, 0.0, 0.0, -0.2, 0.0, 0.0]),
+                vmax=1.2, amax=0.6, rho=1.3, rho_psi=0.7, flags=flags)
+
+
+def random_state(pb, B, seed=1, scale=1.0):
+    """A generic state: random coefficients, multipliers, angles and distances."""
+    rng = np.random.default_rng(seed)
+    st = oracle.empty_state(pb, B)
+    nv = pb["nv"]
+    line_x = np.linspace(pb["bx"][0], pb["bx"][3], nv)
+    line_y = np.linspace(pb["by"][0], pb["by"][3], nv)
+    st["cx"][:] = line_x + rng.normal(0, 0.8 * scale, (B, nv))
+    st["cy"][:] = line_y + rng.normal(0, 0.8 * scale, (B, nv))
+    st["cc"][:] = 1.0 + rng.normal(0, 0.2, (B, nv))
+    st["cs"][:] = rng.normal(0, 0.2, (B, nv))
+    st["cpsi"][:] = rng.normal(0, 0.4, (B, nv))
+    st["lam"][:] = rng.normal(0, 0.3 * scale, st["lam"].shape)
+    st["lampsi"][:] = rng.normal(0, 0.1 * scale, st["lampsi"].shape)
+    st["alpha"][:] = rng.uniform(-np.pi, np.pi, st["alpha"].shape)
+    st["d"][:] = rng.uniform(1.0, 2.0, st["d"].shape)
+    for k in ("av", "aa"):
+        st[k][:] = rng.uniform(-np.pi, np.pi, st[k].shape)
+    for k in ("dv", "da"):
+        st[k][:] = rng.uniform(0.0, 1.0, st[k].shape)
+    return st
+
+
+# ---------------------------------------------------------------- basis (eq. param)
+
+def test_basis_matches_scipy_bernstein():
+    """P, Pdot, Pddot equal SciPy's Bernstein polynomials and derivatives."""
+    for q, nv, tf in ((100, 11, 30.0), (12, 8, 6.0), (37, 5, 2.5)):
+        P, Pd, Pdd = oracle.basis(q, nv, tf)
+        S, Sd, Sdd = bernstein_scipy(q, nv, tf)
+        np.testing.assert_allclose(P, S, atol=1e-14)
+        np.testing.assert_allclose(Pd, Sd, atol=1e-13 * nv / tf)
+        np.testing.assert_allclose(Pdd, Sdd, atol=1e-12 * nv * nv / tf ** 2)
+
+
+def test_basis_golden_closed_forms():
+    """Degree-10 values at tau = 0, 1/2, 1 (exact rationals, tests/golden)."""
+    g = json.load(open(os.path.join(GOLDEN, "bernstein_degree10.json")))
+    P, Pd, Pdd = oracle.basis(3, g["degree"] + 1, float(g["tf"]))
+    f = lambda key: np.array([float(Fraction(v)) for v in g[key]])
+    np.testing.assert_allclose(P[0], f("P_tau0"), atol=1e-15)
+    np.testing.assert_allclose(P[1], f("P_tau_half"), atol=1e-15)
+    np.testing.assert_allclose(P[2], f("P_tau1"), atol=1e-15)
+    np.testing.assert_allclose(Pd[0], f("Pd_tau0"), atol=1e-15)
+    np.testing.assert_allclose(Pd[2], f("Pd_tau1"), atol=1e-15)
+    np.testing.assert_allclose(Pdd[0], f("Pdd_tau0"), atol=1e-15)
+
+
+def test_basis_invariants():
+    """Partition of unity; derivative rows sum to zero; second-order finite
+    differences of P approach Pdot."""
+    q, nv, tf = 100, 11, 30.0
+    P, Pd, Pdd = oracle.basis(q, nv, tf)
+    np.testing.assert_allclose(P.sum(1), 1.0, atol=1e-14)
+    np.testing.assert_allclose(Pd.sum(1), 0.0, atol=1e-14)
+    np.testing.assert_allclose(Pdd.sum(1), 0.0, atol=1e-14)
+    qf = 4001
+    Pf, Pdf, _ = oracle.basis(qf, nv, tf)
+    h = tf / (qf - 1)
+    fd = (Pf[2:] - Pf[:-2]) / (2 * h)
+    np.testing.assert_allclose(fd, Pdf[1:-1], atol=2e-5)
+
+
+# ---------------------------------------------------------------- xi1, xi2 QPs
+
+@pytest.mark.parametrize("flags", [0, oracle.Q_CS_ZERO])
+def test_xi1_equals_nullspace_qp(flags):
+    """Step xi1 (eq. zeta_1_sepration_1 through over_2) equals the null-space
+    minimiser of the same objective written row by row."""
+    pb = tiny_problem(flags=flags)
+    ref = PaperProblem(pb)
+    st = random_state(pb, 3)
+    orc = oracle.Oracle(pb)
+    before = {k: v.copy() for k, v in st.items()}
+    orc.step(oracle.STEP_XI1, st)
+    nv = pb["nv"]
+    for l in range(3):
+        xi_ref = ref.xi1_solution(before, l)
+        xi = np.concatenate([st["cx"][l], st["cc"][l], st["cy"][l], st["cs"][l]])
+        np.testing.assert_allclose(xi, xi_ref, atol=1e-8, rtol=1e-8)
+        J = ref.xi1_objective(before, l)
+        # the minimiser is not beaten by feasible perturbations (sign of the
+        # KKT right-hand side)
+        rng = np.random.default_rng(l)
+        from scipy.linalg import null_space
+        Abig = np.zeros((12, 4 * nv))
+        Abig[:6, :nv] = ref.A
+        Abig[6:, 2 * nv:3 * nv] = ref.A
+        Z = null_space(Abig)
+        for _ in range(5):
+            assert J(xi) <= J(xi + Z @ rng.normal(0, 1e-3, Z.shape[1])) + 1e-12
+
+
+def test_xi1_boundary_conditions_exact():
+    """A xi1 = b to FP64 rounding (eq. reform_eq)."""
+    pb = tiny_problem()
+    st = random_state(pb, 4)
+    orc = oracle.Oracle(pb)
+    orc.step(oracle.STEP_XI1, st)
+    ref = PaperProblem(pb)
+    for l in range(4):
+        np.testing.assert_allclose(ref.A @ st["cx"][l], pb["bx"], atol=1e-11)
+        np.testing.assert_allclose(ref.A @ st["cy"][l], pb["by"], atol=1e-11)
+
+
+@pytest.mark.parametrize("flags", [0, oracle.PSI_NO_UNWRAP])
+def test_xi2_equals_nullspace_qp(flags):
+    """Step xi2 (eq. compute_convex_surrogate) equals the null-space minimiser."""
+    pb = tiny_problem(flags=flags)
+    ref = PaperProblem(pb)
+    st = random_state(pb, 3, seed=7)
+    orc = oracle.Oracle(pb)
+    before = {k: v.copy() for k, v in st.items()}
+    orc.step(oracle.STEP_XI2, st)
+    for l in range(3):
+        np.testing.assert_allclose(st["cpsi"][l], ref.xi2_solution(before, l), atol=1e-9, rtol=1e-9)
+        np.testing.assert_allclose(ref.A @ st["cpsi"][l], pb["bpsi"], atol=1e-11)
+        np.testing.assert_allclose(st["psihat"][l], ref.psi_hat(before, l), atol=1e-13)
+
+
+def test_psi_hat_branch():
+    """Default psi_hat is atan2(s, c) up to a multiple of 2 pi and lies within
+    pi of the current heading; the literal reading lies in (-pi, pi]."""
+    pb = tiny_problem()
+    st = random_state(pb, 2, seed=3)
+    st["cpsi"][:] += 2.5
+    ref = PaperProblem(pb)
+    orc = oracle.Oracle(pb)
+    before = {k: v.copy() for k, v in st.items()}
+    orc.step(oracle.STEP_XI2, st)
+    for l in range(2):
+        c, s = ref.P @ before["cc"][l], ref.P @ before["cs"][l]
+        psi = ref.P @ before["cpsi"][l]
+        k = (st["psihat"][l] - np.arctan2(s, c)) / (2 * np.pi)
+        np.testing.assert_allclose(k, np.round(k), atol=1e-12)
+        assert np.all(np.abs(st["psihat"][l] - psi) <= np.pi + 1e-12)
+
+
+# ---------------------------------------------------------------- xi3, xi4 closed forms
+
+def _project(pb, st):
+    orc = oracle.Oracle(pb)
+    orc.step(oracle.STEP_XI3, st)
+    orc.step(oracle.STEP_XI4, st)
+    return orc
+
+
+def test_projection_circle_brute_force():
+    """a = b: (alpha, d) of eqs. (zeta_2) and (compute_zeta_3) is the exact
+    minimiser over alpha and d >= 1, checked on a dense grid."""
+    pb = tiny_problem(a_eq_b=True, n=2, m=2)
+    st = random_state(pb, 2, seed=11)
+    _project(pb, st)
+    ref = PaperProblem(pb)
+    al = np.linspace(-np.pi, np.pi, 3601)
+    ds = np.linspace(1.0, 6.0, 2001)
+    for l in range(2):
+        x, y, psi = ref.P @ st["cx"][l], ref.P @ st["cy"][l], ref.P @ st["cpsi"][l]
+        for i in range(ref.m):
+            for j in range(ref.n):
+                e = i * ref.n + j
+                for t in range(0, ref.q, 3):
+                    xt = x[t] + ref.r[i] * np.cos(psi[t]) - ref.ox[j, t]
+                    yt = y[t] + ref.r[i] * np.sin(psi[t]) - ref.oy[j, t]
+                    a = ref.a[j]
+                    cost = (xt - a * ds[:, None] * np.cos(al)) ** 2 + (yt - a * ds[:, None] * np.sin(al)) ** 2
+                    best = cost.min()
+                    got = (xt - a * st["d"][l, e, t] * np.cos(st["alpha"][l, e, t])) ** 2 + \
+                          (yt - a * st["d"][l, e, t] * np.sin(st["alpha"][l, e, t])) ** 2
+                    assert got <= best + 1e-9
+                    assert st["d"][l, e, t] >= 1.0
+
+
+def test_projection_ellipse_recovers_constructed_points():
+    """a != b: points built as (a s cos th, b s sin th) give alpha = th and
+    d = max(1, s) (elliptic-angle reading of eq. zeta_2)."""
+    pb = tiny_problem(m=1, n=1, q=40, dynamic=False, seed=2)
+    pb["r"] = np.zeros(1)
+    ref = PaperProblem(pb)
+    rng = np.random.default_rng(4)
+    th = rng.uniform(-np.pi * 0.999, np.pi * 0.999, ref.q)
+    s = rng.uniform(0.2, 3.0, ref.q)
+    xt = ref.a[0] * s * np.cos(th)
+    yt = ref.b[0] * s * np.sin(th)
+    # a trajectory that passes exactly through these relative positions
+    st = oracle.empty_state(pb, 1)
+    target_x, target_y = ref.ox[0] + xt, ref.oy[0] + yt
+    st["cx"][0] = np.linalg.lstsq(ref.P, target_x, rcond=None)[0]
+    st["cy"][0] = np.linalg.lstsq(ref.P, target_y, rcond=None)[0]
+    # evaluate the actual relative positions of that polynomial
+    xr = ref.P @ st["cx"][0] - ref.ox[0]
+    yr = ref.P @ st["cy"][0] - ref.oy[0]
+    _project(pb, st)
+    th_r = np.arctan2(yr / ref.b[0], xr / ref.a[0])
+    s_r = np.sqrt((xr / ref.a[0]) ** 2 + (yr / ref.b[0]) ** 2)
+    np.testing.assert_allclose(np.cos(st["alpha"][0, 0]), np.cos(th_r), atol=1e-12)
+    np.testing.assert_allclose(np.sin(st["alpha"][0, 0]), np.sin(th_r), atol=1e-12)
+    np.testing.assert_allclose(st["d"][0, 0], np.maximum(1.0, s_r), atol=1e-12)
+
+
+def test_distance_is_exact_1d_minimiser():
+    """At the oracle's alpha, d_ij is the minimiser over d >= 1 of eq.
+    (compute_zeta_3); d_v, d_a minimise eqs. (compute_dv), (compute_da) over
+    [0, 1] (brute force)."""
+    pb = tiny_problem(m=2, n=2)
+    st = random_state(pb, 2, seed=21)
+    _project(pb, st)
+    ref = PaperProblem(pb)
+    grid01 = np.linspace(0.0, 1.0, 50001)
+    unit = np.linspace(0.0, 1.0, 10001)
+    for l in range(2):
+        x, y, psi = ref.P @ st["cx"][l], ref.P @ st["cy"][l], ref.P @ st["cpsi"][l]
+        xd, yd = ref.Pd @ st["cx"][l], ref.Pd @ st["cy"][l]
+        xdd, ydd = ref.Pdd @ st["cx"][l], ref.Pdd @ st["cy"][l]
+        for i in range(ref.m):
+            for j in range(ref.n):
+                e = i * ref.n + j
+                for t in range(ref.q):
+                    xt = x[t] + ref.r[i] * np.cos(psi[t]) - ref.ox[j, t]
+                    yt = y[t] + ref.r[i] * np.sin(psi[t]) - ref.oy[j, t]
+                    ca, sa = np.cos(st["alpha"][l, e, t]), np.sin(st["alpha"][l, e, t])
+                    top = 2.0 + 2.0 * np.hypot(xt, yt) / min(ref.a[j], ref.b[j])
+                    g = 1.0 + (top - 1.0) * grid01
+                    f = (xt - ref.a[j] * g * ca) ** 2 + (yt - ref.b[j] * g * sa) ** 2
+                    assert abs(g[f.argmin()] - st["d"][l, e, t]) <= (top - 1.0) / 50000 + 1e-9
+        for t in range(ref.q):
+            for (vx, vy, al, d, lim) in ((xd[t], yd[t], st["av"][l, t], st["dv"][l, t], pb["vmax"]),
+                                         (xdd[t], ydd[t], st["aa"][l, t], st["da"][l, t], pb["amax"])):
+                assert abs(al - atan2z(vy, vx)) <= 1e-11
+                f = (vx - lim * unit * np.cos(al)) ** 2 + (vy - lim * unit * np.sin(al)) ** 2
+                assert abs(unit[f.argmin()] - d) <= 1e-4 + 1e-12
+                assert 0.0 <= d <= 1.0
+
+
+def test_velocity_projection_is_disc_projection():
+    """(vmax d_v cos a_v, vmax d_v sin a_v) is the Euclidean projection of the
+    velocity onto the disc of radius vmax (brute force over a polar grid)."""
+    pb = tiny_problem()
+    st = random_state(pb, 1, seed=8, scale=3.0)
+    _project(pb, st)
+    ref = PaperProblem(pb)
+    xd, yd = ref.Pd @ st["cx"][0], ref.Pd @ st["cy"][0]
+    rr = np.linspace(0, pb["vmax"], 601)[:, None]
+    th = np.linspace(-np.pi, np.pi, 1441)[None, :]
+    gx, gy = (rr * np.cos(th)).ravel(), (rr * np.sin(th)).ravel()
+    for t in range(ref.q):
+        px = pb["vmax"] * st["dv"][0, t] * np.cos(st["av"][0, t])
+        py = pb["vmax"] * st["dv"][0, t] * np.sin(st["av"][0, t])
+        best = ((gx - xd[t]) ** 2 + (gy - yd[t]) ** 2).min()
+        assert (px - xd[t]) ** 2 + (py - yd[t]) ** 2 <= best + 1e-10
+
+
+def test_zero_vector_angle_rule():
+    """atan2(0, 0) := 0 on every projection (reading of an undefined angle)."""
+    pb = tiny_problem(m=1, n=1, q=12, dynamic=False)
+    pb["r"] = np.zeros(1)
+    pb["bx"] = np.zeros(6)
+    pb["by"] = np.zeros(6)
+    pb["ox"] = np.zeros((1, 12))
+    pb["oy"] = np.zeros((1, 12))
+    st = oracle.empty_state(pb, 1)          # zero coefficients: x = y = 0 exactly
+    _project(pb, st)
+    assert np.all(st["alpha"] == 0.0) and np.all(st["av"] == 0.0) and np.all(st["aa"] == 0.0)
+    assert np.all(st["d"] == 1.0) and np.all(st["dv"] == 0.0)
+
+
+# ---------------------------------------------------------------- multipliers
+
+def test_lambda_update_is_penalty_gradient_step():
+    """eq. (update_lambda_1): lambda_new = lambda - grad_xi of
+    (rho/2)||F xi - g||^2, with the gradient taken numerically from the
+    row-wise penalty; eq. (update_lambda_psi) with the consistent sign."""
+    pb = tiny_problem()
+    ref = PaperProblem(pb)
+    st = random_state(pb, 2, seed=31)
+    st["psihat"][:] = np.random.default_rng(0).normal(0, 0.5, st["psihat"].shape)
+    orc = oracle.Oracle(pb)
+    before = {k: v.copy() for k, v in st.items()}
+    orc.step(oracle.STEP_LAMBDA, st)
+    nv, rho = pb["nv"], pb["rho"]
+    for l in range(2):
+        psi = ref.P @ before["cpsi"][l]
+        for axis in (0, 1):
+            xi = np.concatenate([before["cx" if axis == 0 else "cy"][l], before["cc" if axis == 0 else "cs"][l]])
+            pen = lambda z: 0.5 * rho * np.sum(ref.penalty_rows(z, axis, before, l, psi) ** 2)
+            h = 1e-6
+            grad = np.array([(pen(xi + h * e) - pen(xi - h * e)) / (2 * h) for e in np.eye(2 * nv)])
+            np.testing.assert_allclose(st["lam"][l, axis * 2 * nv:(axis + 1) * 2 * nv],
+                                       before["lam"][l, axis * 2 * nv:(axis + 1) * 2 * nv] - grad,
+                                       atol=1e-5 * (1 + np.abs(grad).max()))
+        expect = before["lampsi"][l] - pb["rho_psi"] * ref.P.T @ (psi - before["psihat"][l])
+        np.testing.assert_allclose(st["lampsi"][l], expect, atol=1e-12)
+
+
+# ---------------------------------------------------------------- whole-iteration invariants
+
+def _lag(orc, st):
+    return orc.lagrangian(st)
+
+
+@pytest.mark.parametrize("flags", [0, oracle.XTILDE_SLACK])
+def test_lagrangian_decreases_over_exact_substeps(flags):
+    """xi1 and xi4 are exact minimisations of eq. (reform_bergman) at fixed
+    multipliers, so L_rho cannot rise across them; xi3 is exact too when a = b
+    and x~ uses the slack copies."""
+    pb = tiny_problem(flags=flags, a_eq_b=bool(flags & oracle.XTILDE_SLACK))
+    orc = oracle.Oracle(pb)
+    st = random_state(pb, 4, seed=13)
+    orc.step(oracle.STEP_XI3, st)
+    orc.step(oracle.STEP_XI4, st)
+    orc.step(oracle.STEP_XI1, st)          # start from a point that meets the BCs
+    for _ in range(6):
+        L0 = _lag(orc, st)
+        orc.step(oracle.STEP_XI1, st)
+        L1 = _lag(orc, st)
+        assert np.all(L1 <= L0 + 1e-12 * np.abs(L0) + 1e-12)
+        orc.step(oracle.STEP_XI2, st)
+        L2 = _lag(orc, st)
+        orc.step(oracle.STEP_XI3, st)
+        L3 = _lag(orc, st)
+        if flags & oracle.XTILDE_SLACK:
+            assert np.all(L3 <= L2 + 1e-12 * np.abs(L2) + 1e-12)
+        orc.step(oracle.STEP_XI4, st)
+        L4 = _lag(orc, st)
+        assert np.all(L4 <= L3 + 1e-12 * np.abs(L3) + 1e-12)
+        orc.step(oracle.STEP_LAMBDA, st)
+
+
+def _solve(pb, init, K):
+    orc = oracle.Oracle(pb)
+    st = oracle.state_from(pb, init)
+    h = orc.solve(st, K, hist=True)
+    return orc, st, h
+
+
+def test_solve_equals_step_sequence():
+    """amo_solve = initial xi3, xi4 followed by K x (xi1, xi2, xi3, xi4, lambda)."""
+    pb, init = inputs.workload("c1", batch=3)
+    orc, st, _ = _solve(pb, init, 7)
+    st2 = oracle.state_from(pb, init)
+    orc.step(oracle.STEP_XI3, st2)
+    orc.step(oracle.STEP_XI4, st2)
+    for _ in range(7):
+        for s in (1, 2, 3, 4, 5):
+            orc.step(s, st2)
+    for k in st:
+        np.testing.assert_array_equal(st[k], st2[k])
+
+
+def test_invariants_after_solve():
+    """After K iterations: BCs exact, d >= 1, d_v and d_a in [0, 1], and each
+    trajectory's collision residual no larger than after the first iteration."""
+    pb, init = inputs.workload("c1")
+    orc, st, h = _solve(pb, init, 50)
+    res = orc.residuals(st)
+    assert res[:, 6].max() < 1e-10
+    assert st["d"].min() >= 1.0
+    assert st["dv"].min() >= 0.0 and st["dv"].max() <= 1.0
+    assert st["da"].min() >= 0.0 and st["da"].max() <= 1.0
+    assert np.all(h[-1] <= h[0] + 1e-12)
+    assert res[:, 11].max() == 0.0
+
+
+def test_translation_equivariance():
+    """Shifting start, goal, obstacles and initial samples by a constant shifts
+    the result and leaves the multipliers unchanged (P 1 = 1, Pdot 1 = 0)."""
+    pb, init = inputs.workload("c1", batch=4)
+    _, st, _ = _solve(pb, init, 20)
+    dx, dy = 3.25, -1.5
+    pb2 = dict(pb, ox=pb["ox"] + dx, oy=pb["oy"] + dy,
+               bx=pb["bx"] + np.array([dx, 0, 0, dx, 0, 0]), by=pb["by"] + np.array([dy, 0, 0, dy, 0, 0]))
+    init2 = dict(init, cx=init["cx"] + dx, cy=init["cy"] + dy)
+    _, st2, _ = _solve(pb2, init2, 20)
+    np.testing.assert_allclose(st2["cx"], st["cx"] + dx, atol=1e-8)
+    np.testing.assert_allclose(st2["cy"], st["cy"] + dy, atol=1e-8)
+    np.testing.assert_allclose(st2["cpsi"], st["cpsi"], atol=1e-8)
+    np.testing.assert_allclose(st2["lam"], st["lam"], atol=1e-7)
+
+
+def test_mirror_equivariance():
+    """y -> -y (with psi -> -psi, s -> -s) mirrors the result."""
+    pb, init = inputs.workload("c1", batch=4)
+    pb = dict(pb, bpsi=np.array([0.3, 0, 0, -0.2, 0, 0]))
+    init = dict(init, cpsi=np.tile(np.linspace(0.3, -0.2, pb["nv"]), (4, 1)))
+    _, st, _ = _solve(pb, init, 20)
+    pb2 = dict(pb, oy=-pb["oy"], by=-pb["by"], bpsi=-pb["bpsi"])
+    init2 = dict(init, cy=-init["cy"], cpsi=-init["cpsi"])
+    _, st2, _ = _solve(pb2, init2, 20)
+    np.testing.assert_allclose(st2["cx"], st["cx"], atol=1e-8)
+    np.testing.assert_allclose(st2["cy"], -st["cy"], atol=1e-8)
+    np.testing.assert_allclose(st2["cpsi"], -st["cpsi"], atol=1e-8)
+    np.testing.assert_allclose(st2["cs"], -st["cs"], atol=1e-8)
+
+
+def test_batch_permutation_and_independence():
+    """Trajectories are independent problems sharing one KKT matrix (eq. over_3):
+    permuting the batch permutes the result, a trajectory alone equals itself
+    in the batch (bitwise)."""
+    pb, init = inputs.workload("c1", batch=6)
+    _, st, _ = _solve(pb, init, 15)
+    perm = np.array([3, 0, 5, 1, 4, 2])
+    initp = {k: v[perm] for k, v in init.items()}
+    _, stp, _ = _solve(pb, initp, 15)
+    for k in ("cx", "cy", "cpsi", "lam", "alpha", "d"):
+        np.testing.assert_array_equal(stp[k], st[k][perm])
+    init1 = {k: v[4:5] for k, v in init.items()}
+    _, st1, _ = _solve(pb, init1, 15)
+    for k in ("cx", "cy", "cpsi", "lam"):
+        np.testing.assert_array_equal(st1[k][0], st[k][4])
+
+
+def test_no_obstacle_limit_is_min_acceleration_qp():
+    """n = 0 with inactive bounds: the AM iterates tend to the minimum-
+    acceleration QP with the boundary conditions only (eqs. acc_cost,
+    eq_multiagent), solved here by the null-space method; c -> cos psi."""
+    pb, init = inputs.workload("c1", batch=3)
+    pb = dict(pb, ox=np.zeros((0, pb["q"])), oy=np.zeros((0, pb["q"])), oa=np.zeros(0), ob=np.zeros(0))
+    orc, st, _ = _solve(pb, init, 1500)
+    ref = PaperProblem(pb)
+    from tests.paper_ref import nullspace_qp
+    H = ref.Pdd.T @ ref.Pdd
+    for axis, key in ((0, "cx"), (1, "cy")):
+        c_star = nullspace_qp(H, np.zeros(pb["nv"]), ref.A, np.asarray(pb["bx" if axis == 0 else "by"]))
+        for l in range(3):
+            np.testing.assert_allclose(ref.P @ st[key][l], ref.P @ c_star, atol=2e-3)
+    res = orc.residuals(st)
+    assert res[:, 4].max() < 1e-3
+
+
+def test_single_circle_special_case():
+    """m = 1, r = 0, a = b: the collision projection is the Euclidean
+    projection of the robot centre onto each disc (the single-circle case the
+    paper cites as solvable by convex-concave procedure)."""
+    pb = tiny_problem(m=1, n=3, a_eq_b=True, seed=9)
+    pb["r"] = np.zeros(1)
+    st = random_state(pb, 2, seed=4)
+    _project(pb, st)
+    ref = PaperProblem(pb)
+    for l in range(2):
+        x, y = ref.P @ st["cx"][l], ref.P @ st["cy"][l]
+        for j in range(ref.n):
+            dx, dy = x - ref.ox[j], y - ref.oy[j]
+            dist = np.hypot(dx, dy)
+            px = ref.ox[j] + ref.a[j] * st["d"][l, j] * np.cos(st["alpha"][l, j])
+            py = ref.oy[j] + ref.a[j] * st["d"][l, j] * np.sin(st["alpha"][l, j])
+            scale = np.maximum(dist, ref.a[j]) / dist
+            np.testing.assert_allclose(px, ref.ox[j] + dx * scale, atol=1e-12)
+            np.testing.assert_allclose(py, ref.oy[j] + dy * scale, atol=1e-12)
+
+
+def test_final_clearance_brute_force():
+    """Final trajectories with zero collision residual keep every circle of the
+    robot outside the inflated ellipses, so the true rectangle penetrates an
+    un-inflated ellipse by at most the corner excess of the circle cover plus
+    the inflation error (pure geometry, sampled on a fine grid)."""
+    pb, init = inputs.workload("c1", batch=16)
+    orc, st, _ = _solve(pb, init, 100)
+    res = orc.residuals(st)
+    ok = np.where(res[:, 0] < 1e-9)[0]
+    assert len(ok) >= 4
+    cfg = inputs.CONFIGS["c1"]
+    L, W = cfg.length, cfg.width
+    m = len(pb["r"])
+    corner = np.hypot(L / (2 * m), W / 2) - pb["rc"]
+    qf = 1000
+    P, _, _ = oracle.basis(qf, pb["nv"], pb["tf"])
+    s = np.linspace(-0.5, 0.5, 41)
+    body = np.concatenate([np.stack([s * L, np.full_like(s, W / 2)], 1), np.stack([s * L, np.full_like(s, -W / 2)], 1),
+                           np.stack([np.full_like(s, L / 2), s * W], 1), np.stack([np.full_like(s, -L / 2), s * W], 1)])
+    for l in ok:
+        x, y, psi = P @ st["cx"][l], P @ st["cy"][l], P @ st["cpsi"][l]
+        for j in range(len(pb["oa"])):
+            a, b = pb["oa"][j], pb["ob"][j]
+            cx, cy = pb["ox"][j][0], pb["oy"][j][0]        # static obstacles
+            bx = x[:, None] + np.cos(psi)[:, None] * body[None, :, 0] - np.sin(psi)[:, None] * body[None, :, 1]
+            by = y[:, None] + np.sin(psi)[:, None] * body[None, :, 0] + np.cos(psi)[:, None] * body[None, :, 1]
+            lev = np.sqrt(((bx - cx) / a) ** 2 + ((by - cy) / b) ** 2)
+            # penetration depth is bounded by (1 - level) * max semi-axis
+            depth = np.maximum(0.0, 1.0 - lev) * max(a, b)
+            assert depth.max() <= corner + 0.021 + 0.02, (l, j, depth.max())
+
+
+# ---------------------------------------------------------------- failure handling
+
+def test_invalid_problem_rejected():
+    pb = tiny_problem()
+    with pytest.raises(ValueError):
+        oracle.Oracle(dict(pb, rho=0.0))
+    with pytest.raises(ValueError):
+        oracle.Oracle(dict(pb, vmax=-1.0))
+    with pytest.raises(ValueError):
+        oracle.Oracle(dict(pb, q=1))
