@@ -1,0 +1,102 @@
+// am_device.h -- device helpers shared by the iteration kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "am_internal.h"
+
+namespace amk {
+
+template <typename T>
+struct Num;
+
+template <>
+struct Num<float> {
+  static __device__ __forceinline__ float rsqrt(float x) { return rsqrtf(x); }
+  static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
+  static __device__ __forceinline__ float atan2_(float y, float x) { return atan2f(y, x); }
+  static __device__ __forceinline__ void sincos_(float a, float *s, float *c) { sincosf(a, s, c); }
+  static __device__ __forceinline__ float hypot_(float a, float b) { return hypotf(a, b); }
+  static __device__ __forceinline__ float cos_(float a) { return cosf(a); }
+  static __device__ __forceinline__ float sin_(float a) { return sinf(a); }
+};
+
+template <>
+struct Num<double> {
+  static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+  static __device__ __forceinline__ double sqrt_(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double atan2_(double y, double x) { return ::atan2(y, x); }
+  static __device__ __forceinline__ void sincos_(double a, double *s, double *c) { ::sincos(a, s, c); }
+  static __device__ __forceinline__ double hypot_(double a, double b) { return ::hypot(a, b); }
+  static __device__ __forceinline__ double cos_(double a) { return ::cos(a); }
+  static __device__ __forceinline__ double sin_(double a) { return ::sin(a); }
+};
+
+// atan2 with the value 0 for the zero vector (the angle of a zero vector is
+// not defined by the paper; this reading is used everywhere).
+template <typename T>
+__device__ __forceinline__ T atan2z(T y, T x) {
+  return (x == T(0) && y == T(0)) ? T(0) : Num<T>::atan2_(y, x);
+}
+
+// Orders LDS traffic between lanes of one wavefront (the compiler may not
+// move memory operations across it; a wavefront's LDS operations complete
+// in issue order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__host__ __device__ constexpr int pad4(int v) { return (v + 3) & ~3; }
+
+// LDS carve-up of the fused kernel, in elements of T.
+struct FusedLds {
+  int ox, oy, op;          // centred obstacle tables [n][q]; per-obstacle params [n][8]
+  int m1, m2, gf;          // [2nv][2nv], [nv][nv], [2nv][2nv]
+  int wave0, wave_stride;  // per-wave areas
+  int total;
+};
+
+// Per-wave vectors, each a multiple of nvp = pad4(nv) elements.
+struct WaveLds {
+  int z, rhs, lam, tr, h, zpsi, lampsi, tpsi, tmp, red;
+};
+
+__host__ __device__ inline WaveLds wave_layout(int nv) {
+  const int p = pad4(nv);
+  WaveLds w;
+  int o = 0;
+  w.z = o; o += 4 * p;       // z of (x, c, y, s)
+  w.rhs = o; o += 4 * p;     // lambda + rho F^T g
+  w.lam = o; o += 4 * p;     // lambda in z coordinates
+  w.tr = o; o += 4 * p;      // F^T (F xi - g)
+  w.h = o; o += 5 * p;       // boundary terms of (x, c), (y, s), psi
+  w.zpsi = o; o += p;
+  w.lampsi = o; o += p;
+  w.tpsi = o; o += p;
+  w.tmp = o; o += p;
+  w.red = o; o += 16 * kRedStride;
+  return w;
+}
+
+__host__ __device__ inline FusedLds fused_layout(int q, int n, int nv) {
+  FusedLds L;
+  int o = 0;
+  L.ox = o; o += pad4(n * q);
+  L.oy = o; o += pad4(n * q);
+  L.op = o; o += 8 * n;
+  L.m1 = o; o += pad4(4 * nv * nv);
+  L.m2 = o; o += pad4(nv * nv);
+  L.gf = o; o += pad4(4 * nv * nv);
+  const WaveLds w = wave_layout(nv);
+  L.wave_stride = pad4(w.red + 16 * kRedStride);
+  L.wave0 = o; o += kWavesPerBlock * L.wave_stride;
+  L.total = o;
+  return L;
+}
+
+// Per-obstacle parameter slots in the op table.
+enum { OP_A = 0, OP_B = 1, OP_A2 = 2, OP_B2 = 3, OP_AB = 4 };
+
+}  // namespace amk

@@ -1,0 +1,70 @@
+// am_internal.h -- types shared by the host API and the HIP kernels of the
+// batched AM trajectory optimizer (not part of the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "am.h"
+
+namespace amk {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kWavesPerBlock = 4;  // fused kernel: one trajectory per wave
+constexpr int kSlots = 2;          // time slots per lane: t = lane + 64*s
+constexpr int kRedStride = 68;     // LDS row stride of the reduction scratch
+
+// One problem of a launch: handle constants, problem data, state, sizes.
+// Pointers to typed data (float or double) are void*; the kernel template
+// reinterprets them.
+struct Desc {
+  // constants built by the setup kernel (orthonormal basis, KKT inverses)
+  const void *U, *V, *W;     // [q][nv]: x = U z, xdot = V z, xddot = W z
+  const void *M1, *H1;       // xi1: [2nv][2nv] and [2nv][6]
+  const void *M2, *H2;       // xi2: [nv][nv] and [nv][6]
+  const void *GF;            // [2nv][2nv] F^T F of one axis in the z basis
+  const double *R, *Rinv;    // z = R c (Bernstein c), [nv][nv]
+  // problem
+  const void *ox, *oy, *oa, *ob;
+  // state (Bernstein coordinates at the boundary)
+  void *cx, *cc, *cy, *cs, *cpsi, *lam, *lampsi;
+  void *alpha, *d, *va, *traj;
+  double bx[6], by[6], bpsi[6];
+  double offx, offy;         // translation applied inside the kernel
+  double rc, vmax, amax, rho, rho_psi;
+  double r[AM_MAX_CIRCLES];
+  int q, nv, m, n, B, K, flags;
+  int blk0, nblk;            // blocks of this problem in a multi-problem grid
+};
+
+// Largest descriptor table the multi-problem launch accepts.
+constexpr int kMaxProblems = 4096;
+
+// Device buffers of a handle (all inside one FP64 and one typed allocation).
+struct Consts {
+  double *P, *Pd, *Pdd;          // [q][nv] Bernstein basis and derivatives
+  double *U, *V, *W;             // [q][nv]
+  double *R, *Rinv;              // [nv][nv]
+  double *G;                     // scratch: 3 Gram matrices [3][nv][nv]
+  double *K1, *K2;               // z-space KKT [N1][N1], [N2][N2]
+  double *A1, *A2;               // Gauss-Jordan work [N][2N]
+  double *M1, *H1, *M2, *H2, *GF;
+  double *K1b_inv, *K2b_inv;     // Bernstein-space inverses (diagnostics)
+  double *status;                // [0]: 0 ok, 1 singular xi1 KKT, 2 singular xi2 KKT
+  void *tU, *tV, *tW, *tM1, *tH1, *tM2, *tH2, *tGF;  // typed copies
+  void *tP, *tPd, *tPdd;
+};
+
+// Launchers (defined in the .hip files).
+hipError_t launch_setup(const am_shape &s, const double *r_dev, const Consts &c, bool f64,
+                        hipStream_t st);
+size_t fused_lds_bytes(int q, int n, int nv, bool f64);
+hipError_t launch_fused(const Desc &single, const Desc *table, int nprob, int nblocks, bool f64,
+                        int nv, hipStream_t st, size_t lds_bytes);
+hipError_t launch_residuals(const Desc &d, const void *P, const void *Pd, const void *Pdd, void *out,
+                            bool f64, int nv, hipStream_t st);
+hipError_t launch_desc_copy(const Desc *host_descs, int count, Desc *dev_dst, hipStream_t st);
+hipError_t launch_plain(const Desc &d, void *ws, size_t ws_bytes, bool f64, int nv, hipStream_t st);
+size_t plain_workspace_bytes(int B, int q, int nv, int m, int n, bool f64);
+
+}  // namespace amk

@@ -1,0 +1,419 @@
+// am_plain.hip -- the AM iteration computed the plain way: one kernel launch
+// per sub-step per iteration, with the method's per-(circle, obstacle, t)
+// state (alpha_ij, d_ij of xi3/xi4, Sec. III-C) and the trajectories held in
+// device memory between launches.  It computes the same iteration as the
+// fused kernel (same basis, same readings) and exists as the reference point
+// for the one-launch form; its projection and target kernels are the
+// bandwidth-bound elementwise part of the method.
+//
+// Per iteration:  xi1 -> evaluate -> xi2 -> project (alpha, d) ->
+//                 targets/residual channels -> reduce + multipliers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "am_device.h"
+#include "am_internal.h"
+
+namespace amk {
+namespace {
+
+constexpr int kThreads = 256;
+
+// Workspace carve-up (elements of T).
+struct PlainWs {
+  size_t rhs, z, lam, zpsi, lampsi, traj8, psi3, psih, alpha, d, va4, chan, total;
+};
+
+__host__ __device__ inline PlainWs plain_layout(int B, int q, int nv, int m, int n) {
+  PlainWs w;
+  size_t o = 0;
+  auto take = [&](size_t cnt) {
+    const size_t at = o;
+    o += (cnt + 63) / 64 * 64;
+    return at;
+  };
+  w.rhs = take(size_t(B) * 4 * nv);
+  w.z = take(size_t(B) * 4 * nv);
+  w.lam = take(size_t(B) * 4 * nv);
+  w.zpsi = take(size_t(B) * nv);
+  w.lampsi = take(size_t(B) * nv);
+  w.traj8 = take(size_t(B) * 8 * q);
+  w.psi3 = take(size_t(B) * 3 * q);
+  w.psih = take(size_t(B) * q);
+  w.alpha = take(size_t(B) * m * n * q);
+  w.d = take(size_t(B) * m * n * q);
+  w.va4 = take(size_t(B) * 4 * q);
+  w.chan = take(size_t(B) * 9 * q);
+  w.total = o;
+  return w;
+}
+
+template <typename T>
+struct Ptrs {
+  T *rhs, *z, *lam, *zpsi, *lampsi, *traj8, *psi3, *psih, *alpha, *d, *va4, *chan;
+};
+
+template <typename T>
+Ptrs<T> ptrs_of(void *ws, const PlainWs &w) {
+  T *b = static_cast<T *>(ws);
+  return Ptrs<T>{b + w.rhs, b + w.z, b + w.lam, b + w.zpsi, b + w.lampsi, b + w.traj8,
+                 b + w.psi3, b + w.psih, b + w.alpha, b + w.d, b + w.va4, b + w.chan};
+}
+
+template <typename T>
+__device__ __forceinline__ T wsum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ---- entry: Bernstein coefficients -> z = R (c - offset), lambda -> R^-T lambda
+template <typename T, int NV>
+__global__ void k_enter(Desc D, Ptrs<T> w) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= D.B * 5 * NV) return;
+  const int l = g / (5 * NV), k = g % (5 * NV), b = k / NV, kk = k % NV;
+  const double *R = D.R, *Ri = D.Rinv;
+  const T *src = static_cast<const T *>(b == 0 ? D.cx : b == 1 ? D.cc : b == 2 ? D.cy : b == 3 ? D.cs : D.cpsi);
+  const double off = b == 0 ? D.offx : (b == 2 ? D.offy : 0.0);
+  double z = 0.0, lz = 0.0;
+  for (int j = kk; j < NV; ++j) z += R[kk * NV + j] * (double(src[size_t(l) * NV + j]) - off);
+  if (b < 4) {
+    const T *gl = static_cast<const T *>(D.lam) + size_t(l) * 4 * NV + b * NV;
+    for (int j = 0; j <= kk; ++j) lz += Ri[j * NV + kk] * double(gl[j]);
+    w.z[size_t(l) * 4 * NV + b * NV + kk] = T(z);
+    w.lam[size_t(l) * 4 * NV + b * NV + kk] = T(lz);
+  } else {
+    const T *gl = static_cast<const T *>(D.lampsi) + size_t(l) * NV;
+    for (int j = 0; j <= kk; ++j) lz += Ri[j * NV + kk] * double(gl[j]);
+    w.zpsi[size_t(l) * NV + kk] = T(z);
+    w.lampsi[size_t(l) * NV + kk] = T(lz);
+  }
+}
+
+// ---- xi1: z = M1 rhs + H1 b for both axes
+template <typename T, int NV>
+__global__ void k_xi1(Desc D, Ptrs<T> w) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= D.B * 4 * NV) return;
+  const int l = g / (4 * NV), k = g % (4 * NV), b = k / NV, kk = k % NV, axis = b >> 1;
+  const int I = (b & 1) * NV + kk;
+  const T *M1 = static_cast<const T *>(D.M1), *H1 = static_cast<const T *>(D.H1);
+  const double *bb = axis == 0 ? D.bx : D.by;
+  const double off = axis == 0 ? D.offx : D.offy;
+  T acc = T(0);
+  for (int e = 0; e < 6; ++e) acc += H1[I * 6 + e] * T((e == 0 || e == 3) ? bb[e] - off : bb[e]);
+  const T *r = w.rhs + size_t(l) * 4 * NV + axis * 2 * NV;
+  for (int J = 0; J < 2 * NV; ++J) acc += M1[I * 2 * NV + J] * r[J];
+  w.z[size_t(l) * 4 * NV + k] = acc;
+}
+
+// ---- trajectories x, xdot, xddot, c, y, ydot, yddot, s on the grid
+template <typename T, int NV>
+__global__ void k_eval(Desc D, Ptrs<T> w) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= D.B * D.q) return;
+  const int l = g / D.q, t = g % D.q, q = D.q;
+  const T *U = static_cast<const T *>(D.U) + t * NV, *V = static_cast<const T *>(D.V) + t * NV,
+          *W = static_cast<const T *>(D.W) + t * NV;
+  const T *z = w.z + size_t(l) * 4 * NV;
+  T v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < NV; ++k) {
+    v[0] += U[k] * z[k]; v[1] += V[k] * z[k]; v[2] += W[k] * z[k]; v[3] += U[k] * z[NV + k];
+    v[4] += U[k] * z[2 * NV + k]; v[5] += V[k] * z[2 * NV + k]; v[6] += W[k] * z[2 * NV + k];
+    v[7] += U[k] * z[3 * NV + k];
+  }
+  T *o = w.traj8 + size_t(l) * 8 * q + t;
+  for (int c = 0; c < 8; ++c) o[c * q] = v[c];
+}
+
+// ---- heading trajectory psi = U z_psi with cos, sin
+template <typename T, int NV>
+__global__ void k_eval_psi(Desc D, Ptrs<T> w) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= D.B * D.q) return;
+  const int l = g / D.q, t = g % D.q, q = D.q;
+  const T *U = static_cast<const T *>(D.U) + t * NV;
+  T p = T(0);
+  for (int k = 0; k < NV; ++k) p += U[k] * w.zpsi[size_t(l) * NV + k];
+  T s, c;
+  Num<T>::sincos_(p, &s, &c);
+  T *o = w.psi3 + size_t(l) * 3 * q + t;
+  o[0] = p;
+  o[q] = c;
+  o[2 * q] = s;
+  w.psih[size_t(l) * q + t] = p;
+}
+
+// ---- xi2 (one wavefront per trajectory): psi_hat, heading QP, psi
+template <typename T, int NV>
+__global__ void k_xi2(Desc D, Ptrs<T> w) {
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (l >= D.B) return;
+  const int q = D.q;
+  const bool unwrap = !(D.flags & AM_PSI_NO_UNWRAP);
+  const T *U = static_cast<const T *>(D.U), *M2 = static_cast<const T *>(D.M2),
+          *H2 = static_cast<const T *>(D.H2);
+  const T *tr = w.traj8 + size_t(l) * 8 * q;
+  T *p3 = w.psi3 + size_t(l) * 3 * q, *ph = w.psih + size_t(l) * q;
+  T part[NV];
+  for (int k = 0; k < NV; ++k) part[k] = T(0);
+  for (int t = lane; t < q; t += 64) {
+    const T c = tr[3 * q + t], s = tr[7 * q + t], p = p3[t], cp = p3[q + t], sp = p3[2 * q + t];
+    const T h = unwrap ? p + atan2z(s * cp - c * sp, c * cp + s * sp) : atan2z(s, c);
+    ph[t] = h;
+    for (int k = 0; k < NV; ++k) part[k] += U[t * NV + k] * h;
+  }
+  T rhs[NV];
+  for (int k = 0; k < NV; ++k) rhs[k] = w.lampsi[size_t(l) * NV + k] + T(D.rho) * wsum(part[k]);
+  T zp[NV];
+  for (int k = 0; k < NV; ++k) {
+    T acc = T(0);
+    for (int e = 0; e < 6; ++e) acc += H2[k * 6 + e] * T(D.bpsi[e]);
+    for (int j = 0; j < NV; ++j) acc += M2[k * NV + j] * rhs[j];
+    zp[k] = acc;
+  }
+  if (lane < NV) w.zpsi[size_t(l) * NV + lane] = zp[lane];
+  for (int t = lane; t < q; t += 64) {
+    T p = T(0);
+    for (int k = 0; k < NV; ++k) p += U[t * NV + k] * zp[k];
+    T s, c;
+    Num<T>::sincos_(p, &s, &c);
+    p3[t] = p;
+    p3[q + t] = c;
+    p3[2 * q + t] = s;
+  }
+}
+
+// ---- xi3/xi4: alpha_ij, d_ij for every (l, i, j, t); alpha_v, d_v, alpha_a, d_a
+template <typename T>
+__global__ void k_project(Desc D, Ptrs<T> w) {
+  const size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int q = D.q, m = D.m, n = D.n;
+  const size_t nobs = size_t(D.B) * m * n * q;
+  const bool slack = D.flags & AM_XTILDE_SLACK, literal = D.flags & AM_ALPHA_LITERAL;
+  if (g < nobs) {
+    const int t = int(g % q);
+    const size_t row = g / q;           // l * m n + (i n + j)
+    const int ij = int(row % (size_t(m) * n)), i = ij / n, j = ij % n;
+    const int l = int(row / (size_t(m) * n));
+    const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
+    const T ux = slack ? tr[3 * q + t] : p3[q + t], uy = slack ? tr[7 * q + t] : p3[2 * q + t];
+    const T ri = T(D.r[i]);
+    const T xt = tr[t] + ri * ux - (static_cast<const T *>(D.ox)[j * q + t] - T(D.offx));
+    const T yt = tr[4 * q + t] + ri * uy - (static_cast<const T *>(D.oy)[j * q + t] - T(D.offy));
+    const T a = static_cast<const T *>(D.oa)[j] + T(D.rc), b = static_cast<const T *>(D.ob)[j] + T(D.rc);
+    const T al = literal ? atan2z(yt, xt) : atan2z(a * yt, b * xt);
+    T sa, ca;
+    Num<T>::sincos_(al, &sa, &ca);
+    const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
+    w.alpha[g] = al;
+    w.d[g] = dd;
+  } else if (g < nobs + size_t(D.B) * q) {
+    const size_t h = g - nobs;
+    const int l = int(h / q), t = int(h % q);
+    const T *tr = w.traj8 + size_t(l) * 8 * q;
+    const T xd = tr[q + t], yd = tr[5 * q + t], xdd = tr[2 * q + t], ydd = tr[6 * q + t];
+    const T av = atan2z(yd, xd), aa = atan2z(ydd, xdd);
+    T sv, cv, sa, ca;
+    Num<T>::sincos_(av, &sv, &cv);
+    Num<T>::sincos_(aa, &sa, &ca);
+    T *o = w.va4 + size_t(l) * 4 * q + t;
+    o[0] = av;
+    o[q] = fmin(T(1), fmax(T(0), (xd * cv + yd * sv) / T(D.vmax)));
+    o[2 * q] = aa;
+    o[3 * q] = fmin(T(1), fmax(T(0), (xdd * ca + ydd * sa) / T(D.amax)));
+  }
+}
+
+// ---- residual channels of F xi - g per (l, t), reading alpha and d
+template <typename T>
+__global__ void k_targets(Desc D, Ptrs<T> w) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= D.B * D.q) return;
+  const int l = g / D.q, t = g % D.q, q = D.q, m = D.m, n = D.n;
+  const bool slack = D.flags & AM_XTILDE_SLACK;
+  const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
+  const T x = tr[t], c = tr[3 * q + t], y = tr[4 * q + t], s = tr[7 * q + t];
+  const T cp = p3[q + t], sp = p3[2 * q + t];
+  const T ux = slack ? c : cp, uy = slack ? s : sp;
+  T Dx = 0, Dy = 0, DRx = 0, DRy = 0;
+  const T *al = w.alpha + size_t(l) * m * n * q, *dd = w.d + size_t(l) * m * n * q;
+  for (int i = 0; i < m; ++i) {
+    const T ri = T(D.r[i]);
+    T sx = 0, sy = 0;
+    for (int j = 0; j < n; ++j) {
+      const size_t e = size_t(i * n + j) * q + t;
+      const T a = static_cast<const T *>(D.oa)[j] + T(D.rc), b = static_cast<const T *>(D.ob)[j] + T(D.rc);
+      const T oxj = static_cast<const T *>(D.ox)[j * q + t] - T(D.offx);
+      const T oyj = static_cast<const T *>(D.oy)[j * q + t] - T(D.offy);
+      T sa, ca;
+      Num<T>::sincos_(al[e], &sa, &ca);
+      // deviation of the target g from the current circle centre
+      sx += oxj + a * dd[e] * ca - (x + ri * ux);
+      sy += oyj + b * dd[e] * sa - (y + ri * uy);
+    }
+    Dx += sx; Dy += sy; DRx += ri * sx; DRy += ri * sy;
+  }
+  T s1 = 0, s2 = 0;
+  for (int i = 0; i < m; ++i) { s1 += T(D.r[i]); s2 += T(D.r[i]) * T(D.r[i]); }
+  s1 *= T(n);
+  s2 *= T(n);
+  const T *va = w.va4 + size_t(l) * 4 * q;
+  T sv, cv, sa, ca;
+  Num<T>::sincos_(va[t], &sv, &cv);
+  Num<T>::sincos_(va[2 * q + t], &sa, &ca);
+  const T vm = T(D.vmax), am = T(D.amax);
+  const T dc = c - cp, ds = s - sp;
+  const T k1 = slack ? T(0) : s1, k2 = (slack ? T(0) : s2) + T(1);
+  T *ch = w.chan + size_t(l) * 9 * q + t;
+  ch[0] = tr[q + t] - vm * va[q + t] * cv;          // xdot - g_v
+  ch[q] = tr[2 * q + t] - am * va[3 * q + t] * ca;  // xddot - g_a
+  ch[2 * q] = k1 * dc - Dx;                         // sum_ij (x + r_i c - g_ob)
+  ch[3 * q] = k2 * dc - DRx;                        // sum_ij r_i (...) + (c - cos psi)
+  ch[4 * q] = tr[5 * q + t] - vm * va[q + t] * sv;
+  ch[5 * q] = tr[6 * q + t] - am * va[3 * q + t] * sa;
+  ch[6 * q] = k1 * ds - Dy;
+  ch[7 * q] = k2 * ds - DRy;
+  const T psi_sign = (D.flags & AM_LAMPSI_LITERAL) ? T(-1) : T(1);
+  ch[8 * q] = psi_sign * (p3[t] - w.psih[size_t(l) * q + t]);
+}
+
+// ---- F^T (F xi - g), multipliers and the next right-hand side (one wave
+// per trajectory).  mode 0: initial right-hand side only.
+template <typename T, int NV>
+__global__ void k_contract(Desc D, Ptrs<T> w, int update) {
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (l >= D.B) return;
+  const int q = D.q;
+  const T *U = static_cast<const T *>(D.U), *V = static_cast<const T *>(D.V), *W = static_cast<const T *>(D.W);
+  const T *GF = static_cast<const T *>(D.GF);
+  const T *ch = w.chan + size_t(l) * 9 * q;
+  T part[5 * NV];
+  for (int k = 0; k < 5 * NV; ++k) part[k] = T(0);
+  for (int t = lane; t < q; t += 64) {
+    for (int k = 0; k < NV; ++k) {
+      const T u = U[t * NV + k], v = V[t * NV + k], wv = W[t * NV + k];
+      part[k] += v * ch[t] + wv * ch[q + t] + u * ch[2 * q + t];
+      part[NV + k] += u * ch[3 * q + t];
+      part[2 * NV + k] += v * ch[4 * q + t] + wv * ch[5 * q + t] + u * ch[6 * q + t];
+      part[3 * NV + k] += u * ch[7 * q + t];
+      part[4 * NV + k] += u * ch[8 * q + t];
+    }
+  }
+  T tot[5 * NV];
+  for (int k = 0; k < 5 * NV; ++k) tot[k] = wsum(part[k]);
+  T *lam = w.lam + size_t(l) * 4 * NV, *z = w.z + size_t(l) * 4 * NV;
+  if (lane < 4 * NV) {
+    const int k = lane, b = k / NV, kk = k % NV, axis = b >> 1, I = (b & 1) * NV + kk;
+    T trv = T(0);
+    for (int c = 0; c < 4 * NV; ++c)
+      if (c == k) trv = tot[c];
+    T lv = lam[k];
+    if (update) lv -= T(D.rho) * trv;
+    T gz = T(0);
+    for (int J = 0; J < 2 * NV; ++J) gz += GF[I * 2 * NV + J] * z[axis * 2 * NV + J];
+    lam[k] = lv;
+    w.rhs[size_t(l) * 4 * NV + k] = lv + T(D.rho) * (gz - trv);
+  } else if (update && lane < 5 * NV) {
+    const int kk = lane - 4 * NV;
+    T tp = T(0);
+    for (int c = 0; c < NV; ++c)
+      if (c == kk) tp = tot[4 * NV + c];
+    w.lampsi[size_t(l) * NV + kk] -= T(D.rho_psi) * tp;
+  }
+}
+
+// ---- exit: back to Bernstein coordinates, optional outputs
+template <typename T, int NV>
+__global__ void k_exit(Desc D, Ptrs<T> w) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < D.B * 5 * NV) {
+    const int l = g / (5 * NV), k = g % (5 * NV), b = k / NV, kk = k % NV;
+    const double *R = D.R, *Ri = D.Rinv;
+    const T *zs = b < 4 ? w.z + size_t(l) * 4 * NV + b * NV : w.zpsi + size_t(l) * NV;
+    const T *ls = b < 4 ? w.lam + size_t(l) * 4 * NV + b * NV : w.lampsi + size_t(l) * NV;
+    double c = 0.0, lc = 0.0;
+    for (int j = kk; j < NV; ++j) c += Ri[kk * NV + j] * double(zs[j]);
+    for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(ls[j]);
+    const double off = b == 0 ? D.offx : (b == 2 ? D.offy : 0.0);
+    T *dst = static_cast<T *>(b == 0 ? D.cx : b == 1 ? D.cc : b == 2 ? D.cy : b == 3 ? D.cs : D.cpsi);
+    dst[size_t(l) * NV + kk] = T(c + off);
+    if (b < 4) static_cast<T *>(D.lam)[size_t(l) * 4 * NV + b * NV + kk] = T(lc);
+    else static_cast<T *>(D.lampsi)[size_t(l) * NV + kk] = T(lc);
+  }
+  const int q = D.q;
+  if (g < D.B * q) {
+    const int l = g / q, t = g % q;
+    const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
+    if (D.traj) {
+      T *o = static_cast<T *>(D.traj) + size_t(l) * 3 * q;
+      o[t] = tr[t] + T(D.offx);
+      o[q + t] = tr[4 * q + t] + T(D.offy);
+      o[2 * q + t] = p3[t];
+    }
+    if (D.va) {
+      T *o = static_cast<T *>(D.va) + size_t(l) * 4 * q;
+      const T *v = w.va4 + size_t(l) * 4 * q;
+      for (int c = 0; c < 4; ++c) o[c * q + t] = v[c * q + t];
+    }
+    const size_t mnq = size_t(D.m) * D.n * q;
+    for (int ij = 0; ij < D.m * D.n; ++ij) {
+      const size_t e = size_t(l) * mnq + size_t(ij) * q + t;
+      if (D.alpha) static_cast<T *>(D.alpha)[e] = w.alpha[e];
+      if (D.d) static_cast<T *>(D.d)[e] = w.d[e];
+    }
+  }
+}
+
+inline int blocks_for(size_t work) { return int((work + kThreads - 1) / kThreads); }
+
+template <typename T, int NV>
+hipError_t run(const Desc &D, void *ws, hipStream_t st) {
+  const PlainWs L = plain_layout(D.B, D.q, NV, D.m, D.n);
+  const Ptrs<T> w = ptrs_of<T>(ws, L);
+  const int B = D.B, q = D.q;
+  const size_t nproj = size_t(B) * D.m * D.n * q + size_t(B) * q;
+  const int wave_blocks = (B + 3) / 4;
+  hipLaunchKernelGGL((k_enter<T, NV>), dim3(blocks_for(size_t(B) * 5 * NV)), dim3(kThreads), 0, st, D, w);
+  // step 1: initial xi3, xi4 from the given trajectories
+  hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
+  hipLaunchKernelGGL((k_eval_psi<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
+  hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(nproj)), dim3(kThreads), 0, st, D, w);
+  hipLaunchKernelGGL((k_targets<T>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
+  hipLaunchKernelGGL((k_contract<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w, 0);
+  for (int it = 0; it < D.K; ++it) {
+    hipLaunchKernelGGL((k_xi1<T, NV>), dim3(blocks_for(size_t(B) * 4 * NV)), dim3(kThreads), 0, st, D, w);
+    hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
+    hipLaunchKernelGGL((k_xi2<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w);
+    hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(nproj)), dim3(kThreads), 0, st, D, w);
+    hipLaunchKernelGGL((k_targets<T>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
+    hipLaunchKernelGGL((k_contract<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w, 1);
+  }
+  const size_t exit_work = std::max(size_t(B) * 5 * NV, size_t(B) * q);
+  hipLaunchKernelGGL((k_exit<T, NV>), dim3(blocks_for(exit_work)), dim3(kThreads), 0, st, D, w);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t plain_workspace_bytes(int B, int q, int nv, int m, int n, bool f64) {
+  return plain_layout(B, q, nv, m, n).total * (f64 ? 8 : 4);
+}
+
+hipError_t launch_plain(const Desc &d, void *ws, size_t, bool f64, int nv, hipStream_t st) {
+  if (d.B <= 0) return hipSuccess;
+  if (f64) {
+    if (nv == 11) return run<double, 11>(d, ws, st);
+    if (nv == 8) return run<double, 8>(d, ws, st);
+  } else {
+    if (nv == 11) return run<float, 11>(d, ws, st);
+    if (nv == 8) return run<float, 8>(d, ws, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace amk

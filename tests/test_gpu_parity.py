@@ -1,0 +1,205 @@
+"""GPU library against the FP64 oracle on identical seeded inputs (needs an
+MI355X).  Every call goes through the C-ABI of include/am.h."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2109_13030_amd import inputs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_13030_amd import am
+    am.lib()
+
+
+def _small(name="c1", B=None, **kw):
+    pb, init = inputs.workload(name, batch=B)
+    pb = dict(pb, **kw)
+    return pb, init
+
+
+# ------------------------------------------------------------- setup (FP64 on the GPU)
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_setup_inverse_matches_oracle_kkt(name):
+    """The GPU's FP64 KKT inverses invert the oracle's KKT matrices (eq. over_2)."""
+    from paper_2109_13030_amd import am
+    pb, _ = inputs.workload(name, batch=1)
+    h = am.Handle.for_problem(pb, "f64")
+    k1i, k2i, basis = h.matrices()
+    _, K1, K2 = oracle.Oracle(pb).matrices()
+    P, Pd, Pdd = oracle.basis(pb["q"], pb["nv"], pb["tf"])
+    np.testing.assert_allclose(basis[0], P, atol=1e-14)
+    np.testing.assert_allclose(basis[1], Pd, atol=1e-14)
+    np.testing.assert_allclose(basis[2], Pdd, atol=1e-14)
+    for K, Ki in ((K1, k1i), (K2, k2i)):
+        I = np.eye(K.shape[0])
+        assert np.abs(K @ Ki - I).max() < 1e-8
+        assert np.abs(Ki @ K - I).max() < 1e-8
+
+
+# ------------------------------------------------------------- FP64 GPU = oracle (same algorithm)
+
+def _compare_f64(pb, init, K, tol=1e-8, projections=True):
+    h, p, st = H.run_gpu(pb, init, K, "f64", projections=projections)
+    out = st.numpy()
+    orc, ost = H.run_oracle(pb, init, K)
+    epos, epsi = H.traj_errors(pb, out, orc, ost)
+    assert epos.max() < tol and epsi.max() < tol, (epos.max(), epsi.max())
+    # multipliers (Bernstein coordinates) and slack coefficients as trajectories
+    lam_scale = 1.0 + np.abs(ost["lam"]).max()
+    assert np.abs(out["lam"] - ost["lam"]).max() < 1e3 * tol * lam_scale
+    assert np.abs(out["lam_psi"] - ost["lampsi"]).max() < 1e3 * tol * (1 + np.abs(ost["lampsi"]).max())
+    if projections:
+        # alpha compared through (cos, sin); d directly
+        a_g, a_o = out["alpha"], ost["alpha"]
+        assert np.abs(np.cos(a_g) - np.cos(a_o)).max() < 1e3 * tol
+        assert np.abs(np.sin(a_g) - np.sin(a_o)).max() < 1e3 * tol
+        assert np.abs(out["d"] - ost["d"]).max() < 1e3 * tol * (1 + ost["d"].max())
+        va = out["va"]
+        assert np.abs(va[:, 1] - ost["dv"]).max() < 1e3 * tol
+        assert np.abs(va[:, 3] - ost["da"]).max() < 1e3 * tol
+    x = out["traj"]
+    gx, gy, gp = H.gpu_traj(pb, out)
+    np.testing.assert_allclose(x[:, 0], gx, atol=1e-9)
+    np.testing.assert_allclose(x[:, 1], gy, atol=1e-9)
+    np.testing.assert_allclose(x[:, 2], gp, atol=1e-9)
+    return out, ost
+
+
+def test_c1_f64_matches_oracle():
+    """Config c1 (B = 16, 3 circles, 4 static obstacles, 50 iterations) in FP64."""
+    pb, init = inputs.workload("c1")
+    _compare_f64(pb, init, 50)
+
+
+@pytest.mark.parametrize("flags", [oracle.ALPHA_LITERAL, oracle.XTILDE_SLACK, oracle.PSI_NO_UNWRAP,
+                                   oracle.Q_CS_ZERO, oracle.LAMPSI_LITERAL])
+def test_readings_f64_match_oracle(flags):
+    """Each alternative reading gives the oracle's result (FP64, 10 iterations)."""
+    pb, init = inputs.workload("c1", batch=6)
+    pb = dict(pb, flags=flags)
+    _compare_f64(pb, init, 10)
+
+
+@pytest.mark.parametrize("B,K", [(1, 5), (5, 7), (9, 0), (4, 1)])
+def test_ragged_batches_and_zero_iterations_f64(B, K):
+    """Batches that fill part of a block, and iters = 0 (initial projection only)."""
+    pb, init = inputs.workload("c2", batch=B)
+    _compare_f64(pb, init, K)
+
+
+def test_no_obstacles_and_single_circle_f64():
+    pb, init = inputs.workload("c1", batch=5)
+    pb0 = dict(pb, ox=np.zeros((0, pb["q"])), oy=np.zeros((0, pb["q"])), oa=np.zeros(0), ob=np.zeros(0))
+    _compare_f64(pb0, init, 20, projections=False)
+    pb1 = dict(pb, r=np.zeros(1), ob=pb["oa"].copy())
+    _compare_f64(pb1, init, 20)
+
+
+def test_warm_start_continues_the_iteration_f64():
+    """K1 iterations then K2 more from the returned state = K1 + K2 at once."""
+    from paper_2109_13030_amd import am
+    pb, init = inputs.workload("c1", batch=8)
+    h, p, st = H.run_gpu(pb, init, 30, "f64")
+    st2 = am.DeviceState(st.numpy(), len(pb["r"]), len(pb["oa"]), pb["q"], "f64")
+    am.solve(h, p, st2, 20)
+    a = st2.numpy()
+    _, _, st3 = H.run_gpu(pb, init, 50, "f64", handle=h, problem=p)
+    b = st3.numpy()
+    gx, gy, gp = H.gpu_traj(pb, a)
+    hx, hy, hp = H.gpu_traj(pb, b)
+    assert max(np.abs(gx - hx).max(), np.abs(gy - hy).max(), np.abs(gp - hp).max()) < 1e-8
+
+
+# ------------------------------------------------------------- FP32 against the FP64 oracle
+
+def _fp32_gate(pb, init, K, idx=None, out=None):
+    """FP32 GPU vs FP64 oracle on trajectories idx (all by default)."""
+    if out is None:
+        _, _, st = H.run_gpu(pb, init, K, "f32")
+        out = st.numpy()
+    if idx is None:
+        idx = np.arange(out["cx"].shape[0])
+    sub = H.subset(init, idx)
+    orc, ost, spread = H.conditioning(pb, sub, K)
+    outs = {k: (v[idx] if v is not None else None) for k, v in out.items()}
+    epos, epsi = H.traj_errors(pb, outs, orc, ost)
+    err = np.maximum(epos, epsi)
+    good = spread <= H.COND_FRACTION * H.TOL_POS
+    # the FP32 path meets the tolerance wherever the FP64 problem allows it
+    assert np.all(epos[good] <= H.TOL_POS), (epos[good].max(), np.where(~(epos[good] <= H.TOL_POS)))
+    assert np.all(epsi[good] <= H.TOL_PSI), epsi[good].max()
+    # ill-conditioned trajectories are rare; their error stays bounded by
+    # what the FP64 problem itself amplifies
+    assert good.mean() >= 0.9, good.mean()
+    assert np.all(err[~good] <= np.maximum(H.TOL_POS, 200.0 * spread[~good]) + 1e-3)
+    return epos, epsi, spread
+
+
+def test_c1_f32_matches_oracle():
+    pb, init = inputs.workload("c1")
+    _fp32_gate(pb, init, 50)
+
+
+def test_c2_f32_full_batch_sampled_against_oracle():
+    """Config c2 at its full size (B = 1000, 5 circles, 10 moving obstacles,
+    100 iterations) in the launch the benchmark times; 48 sampled
+    trajectories (first, last, ragged tail and random) checked against the
+    oracle one by one."""
+    pb, init = inputs.workload("c2")
+    _, _, st = H.run_gpu(pb, init, 100, "f32")
+    out = st.numpy()
+    B = out["cx"].shape[0]
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([[0, 1, 2, 3, B - 4, B - 3, B - 2, B - 1],
+                                    rng.choice(B, 40, replace=False)]))
+    _fp32_gate(pb, init, 100, idx, out)
+    # every trajectory keeps the boundary conditions and finite values
+    from paper_2109_13030_amd import am
+    h = am.Handle.for_problem(pb, "f32")
+    p = am.DeviceProblem(pb, "f32")
+    res = am.residuals(h, p, st).cpu().numpy()
+    assert res[:, am.RES_NAMES.index("nonfinite")].max() == 0
+    assert res[:, am.RES_NAMES.index("bc_max")].max() < 1e-3
+
+
+def test_residuals_match_oracle():
+    from paper_2109_13030_amd import am
+    pb, init = inputs.workload("c1", batch=8)
+    h, p, st = H.run_gpu(pb, init, 30, "f64")
+    res = am.residuals(h, p, st).cpu().numpy()
+    orc, ost = H.run_oracle(pb, init, 30)
+    ref = orc.residuals(ost)
+    np.testing.assert_allclose(res, ref, atol=1e-7, rtol=1e-6)
+
+
+def test_multi_problem_launch_equals_single_launches():
+    """Uneven problems in one launch give bit-identical results to one launch
+    per problem (same kernel, same arithmetic)."""
+    import torch
+    from paper_2109_13030_amd import am
+    probs = inputs.uneven_problems("c3", count=5, batch_cap=70)
+    handles, dps, sts, singles = [], [], [], []
+    for pb, init in probs:
+        h = am.Handle.for_problem(pb, "f32")
+        dp = am.DeviceProblem(pb, "f32")
+        handles.append(h)
+        dps.append(dp)
+        sts.append(am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32"))
+        s1 = am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32")
+        am.solve(h, dp, s1, 12)
+        singles.append(s1)
+    ws = torch.empty(am.multi_workspace_size(len(probs)), dtype=torch.uint8, device="cuda")
+    am.solve_multi(handles, dps, sts, 12, ws)
+    torch.cuda.synchronize()
+    for s, s1 in zip(sts, singles):
+        for k in ("cx", "cy", "cpsi", "lam", "lam_psi", "traj"):
+            assert torch.equal(s.t[k], s1.t[k]), k
