@@ -98,7 +98,7 @@ Desc make_desc(const am_handle *h, const am_problem *p, int32_t batch, int32_t i
   d.q = h->shape.q; d.nv = h->shape.nv; d.m = h->shape.m; d.n = h->shape.n_obs;
   d.B = batch; d.K = iters; d.flags = int(h->shape.flags);
   d.blk0 = 0;
-  d.nblk = (batch + amk::kWavesPerBlock - 1) / amk::kWavesPerBlock;
+  d.nblk = (batch + amk::kTrajPerBlock - 1) / amk::kTrajPerBlock;
   return d;
 }
 
@@ -110,6 +110,13 @@ size_t lds_limit() {
 }
 
 }  // namespace
+
+namespace amk {
+int handle_q(const am_handle *h) { return h->shape.q; }
+int handle_nv(const am_handle *h) { return h->shape.nv; }
+int handle_n(const am_handle *h) { return h->shape.n_obs; }
+int handle_dtype(const am_handle *h) { return h->shape.dtype; }
+}  // namespace amk
 
 extern "C" {
 

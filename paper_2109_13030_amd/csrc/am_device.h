@@ -50,10 +50,15 @@ __device__ __forceinline__ void wave_sync() {
 
 __host__ __device__ constexpr int pad4(int v) { return (v + 3) & ~3; }
 
+// Sums exchanged between the two wavefronts of one trajectory.
+enum { XG_PSIH = 0, XG_T1X, XG_T2X, XG_T1Y, XG_T2Y, XG_TPSI, XG_COUNT };
+constexpr int kXchStride = 16;
+
 // LDS carve-up of the fused kernel, in elements of T.
 struct FusedLds {
   int ox, oy, op;          // centred obstacle tables [n][q]; per-obstacle params [n][8]
   int m1, m2, gf;          // [2nv][2nv], [nv][nv], [2nv][2nv]
+  int xch;                 // [traj][half][group][16] exchange area
   int wave0, wave_stride;  // per-wave areas
   int total;
 };
@@ -89,6 +94,7 @@ __host__ __device__ inline FusedLds fused_layout(int q, int n, int nv) {
   L.m1 = o; o += pad4(4 * nv * nv);
   L.m2 = o; o += pad4(nv * nv);
   L.gf = o; o += pad4(4 * nv * nv);
+  L.xch = o; o += kTrajPerBlock * 2 * XG_COUNT * kXchStride;
   const WaveLds w = wave_layout(nv);
   L.wave_stride = pad4(w.red + 16 * kRedStride);
   L.wave0 = o; o += kWavesPerBlock * L.wave_stride;
@@ -97,6 +103,6 @@ __host__ __device__ inline FusedLds fused_layout(int q, int n, int nv) {
 }
 
 // Per-obstacle parameter slots in the op table.
-enum { OP_A = 0, OP_B = 1, OP_A2 = 2, OP_B2 = 3, OP_AB = 4 };
+enum { OP_A = 0, OP_B = 1, OP_A2 = 2, OP_B2 = 3, OP_AB = 4, OP_AMAX = 5 };
 
 }  // namespace amk

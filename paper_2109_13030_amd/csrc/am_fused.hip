@@ -1,23 +1,29 @@
 // am_fused.hip -- the whole batched AM iteration (Sec. III-D) in one launch.
 //
-// One wavefront owns one trajectory for all K iterations; its lanes own the
-// time steps t = lane and t = lane + 64.  Everything the iteration carries
-// (multipliers, coefficients, targets) stays in registers and LDS; global
-// memory is touched only to load the initial state and to store the final
-// one.  The four waves of a 256-thread block share the LDS copy of the
-// problem's obstacle table and KKT operators.
+// Two wavefronts own one trajectory for all K iterations: wave h of the pair
+// holds the time steps t = h*ceil(q/2) + lane.  A 256-thread block carries
+// two trajectories and shares the LDS copy of the problem's obstacle table
+// and KKT operators.  Everything the iteration carries (multipliers,
+// coefficients, targets) stays in registers and LDS; global memory is read
+// for the initial state and written for the final one only.  Sums over t
+// are formed per wave, exchanged through LDS and added in a fixed order, so
+// both waves of a pair hold bit-identical copies of the wave-uniform
+// vectors (coefficients, multipliers, right-hand sides).
 //
 // Algebra used (identical to the paper's steps in exact arithmetic):
 //  * Coefficients live in the orthonormal basis z = R c (P = U R), so
 //    x = U z, xdot = V z, xddot = W z and F^T v is formed with U^T, V^T, W^T.
-//  * The xi3/xi4 closed forms are never evaluated through angles inside the
+//  * The xi3/xi4 closed forms are not evaluated through angles inside the
 //    loop.  With the elliptic angle alpha = atan2(a y~, b x~) the target of a
 //    collision row is g = (x_j, y_j) + (x~, y~) max(1, ab / sqrt(b^2 x~^2 +
 //    a^2 y~^2)) (eqs. zeta_2, compute_zeta_3 with d >= 1), and the velocity
 //    target is the projection of (xdot, ydot) on the disc of radius vmax
 //    (eqs. alpha_v, compute_dv clipped to [0, 1]).  Only the deviation of g
 //    from the current point is accumulated, so residuals are formed without
-//    cancellation.
+//    cancellation.  That deviation is zero for circle centres outside the
+//    ellipse, so obstacles farther from the robot centre than the farthest
+//    circle plus the larger semi-axis are skipped (a wave-wide vote per
+//    obstacle).
 //  * lambda <- lambda - rho F^T (F xi - g) (eq. update_lambda_1) and the next
 //    right-hand side lambda + rho F^T g = lambda + rho (F^T F xi - F^T(F xi - g))
 //    share the single reduction F^T (F xi - g).
@@ -32,12 +38,6 @@ namespace amk {
 namespace {
 
 constexpr int kMaxC = AM_MAX_CIRCLES;
-
-template <typename T, int NV>
-struct Wave {
-  static constexpr int NVP = pad4(NV);
-  T *z, *rhs, *lam, *tr, *h, *zpsi, *lampsi, *tpsi, *tmp, *red;
-};
 
 // Sum over the 64 lanes of G <= 16 per-lane partials.  On return lane k
 // (k < G) holds the sum of partial k (lanes k+16, k+32, k+48 hold it too).
@@ -61,14 +61,21 @@ __device__ __forceinline__ T wave_sum_rows(const T (&p)[G], T *red, int lane) {
 }
 
 template <typename T, int NV>
-__device__ void fused_body(const Desc &D, int l, T *lds, const FusedLds &L, int lane, int wave) {
+__device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds, const FusedLds &L,
+                           int lane, int wave) {
   constexpr int NVP = pad4(NV);
-  const int q = D.q, m = D.m, n = D.n, flags = D.flags;
-  const T rho = T(D.rho), rhop = T(D.rho_psi), vmax = T(D.vmax), amax = T(D.amax);
+  // descriptor fields used in the loop, as locals
+  const int q = Dsrc.q, m = Dsrc.m, n = Dsrc.n, flags = Dsrc.flags, K = Dsrc.K;
+  const T rho = T(Dsrc.rho), rhop = T(Dsrc.rho_psi), vmax = T(Dsrc.vmax), amax = T(Dsrc.amax);
+  const double offx = Dsrc.offx, offy = Dsrc.offy;
   const bool slack = flags & AM_XTILDE_SLACK;
   const bool literal_alpha = flags & AM_ALPHA_LITERAL;
   const bool unwrap = !(flags & AM_PSI_NO_UNWRAP);
   const T psi_sign = (flags & AM_LAMPSI_LITERAL) ? T(-1) : T(1);
+  const int hq = (q + 1) / 2;
+  const int t = half * hq + lane;
+  const bool tv = lane < hq && t < q;
+  const int tt = tv ? t : 0;
 
   const T *ox = lds + L.ox, *oy = lds + L.oy, *op = lds + L.op;
   const T *M1 = lds + L.m1, *M2 = lds + L.m2, *GF = lds + L.gf;
@@ -77,42 +84,40 @@ __device__ void fused_body(const Desc &D, int l, T *lds, const FusedLds &L, int 
   T *vz = wb + wl.z, *vrhs = wb + wl.rhs, *vlam = wb + wl.lam, *vtr = wb + wl.tr, *vh = wb + wl.h;
   T *vzpsi = wb + wl.zpsi, *vlampsi = wb + wl.lampsi, *vtpsi = wb + wl.tpsi, *vtmp = wb + wl.tmp;
   T *red = wb + wl.red;
+  // exchange area of this trajectory: [half][group][16]
+  T *xch = lds + L.xch + (wave >> 1) * 2 * XG_COUNT * kXchStride;
+  T *xmine = xch + half * XG_COUNT * kXchStride;
 
   T rr[kMaxC];
-  T s1 = T(0), s2 = T(0);
+  T s1 = T(0), s2 = T(0), rmax = T(0);
 #pragma unroll
   for (int i = 0; i < kMaxC; ++i) {
-    rr[i] = i < m ? T(D.r[i]) : T(0);
+    rr[i] = i < m ? T(Dsrc.r[i]) : T(0);
     s1 += rr[i];
     s2 += rr[i] * rr[i];
+    rmax = fmax(rmax, fabs(rr[i]));
   }
   s1 *= T(n);   // n sum r_i
   s2 *= T(n);   // n sum r_i^2
 
   // ---- per-lane basis rows (constant for the whole solve)
-  const T *gU = static_cast<const T *>(D.U), *gV = static_cast<const T *>(D.V),
-          *gW = static_cast<const T *>(D.W);
-  T Ub[kSlots][NV], Vb[kSlots][NV], Wb[kSlots][NV];
-  bool tv[kSlots];
+  const T *gU = static_cast<const T *>(Dsrc.U), *gV = static_cast<const T *>(Dsrc.V),
+          *gW = static_cast<const T *>(Dsrc.W);
+  T Ub[NV], Vb[NV], Wb[NV];
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    const int t = lane + kWave * s;
-    tv[s] = t < q;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      Ub[s][k] = tv[s] ? gU[t * NV + k] : T(0);
-      Vb[s][k] = tv[s] ? gV[t * NV + k] : T(0);
-      Wb[s][k] = tv[s] ? gW[t * NV + k] : T(0);
-    }
+  for (int k = 0; k < NV; ++k) {
+    Ub[k] = tv ? gU[tt * NV + k] : T(0);
+    Vb[k] = tv ? gV[tt * NV + k] : T(0);
+    Wb[k] = tv ? gW[tt * NV + k] : T(0);
   }
 
   // ---- boundary terms h = H b (centred positions) and the initial state
-  const double *R = D.R, *Rinv = D.Rinv;
+  const double *R = Dsrc.R, *Rinv = Dsrc.Rinv;
   if (lane < 4 * NV) {
     const int b = lane / NV, kk = lane % NV, axis = b >> 1;
-    const double *bb = axis == 0 ? D.bx : D.by;
-    const double off = axis == 0 ? D.offx : D.offy;
-    const T *H1 = static_cast<const T *>(D.H1);
+    const double *bb = axis == 0 ? Dsrc.bx : Dsrc.by;
+    const double off = axis == 0 ? offx : offy;
+    const T *H1 = static_cast<const T *>(Dsrc.H1);
     const int I = (b & 1) * NV + kk;
     double hsum = 0.0;
     for (int e = 0; e < 6; ++e) {
@@ -122,182 +127,186 @@ __device__ void fused_body(const Desc &D, int l, T *lds, const FusedLds &L, int 
     vh[b * NVP + kk] = T(hsum);
     // z = R (c - off): the basis reproduces constants, so shifting all
     // coefficients of a position shifts its curve
-    const T *src = static_cast<const T *>(b == 0 ? D.cx : (b == 1 ? D.cc : (b == 2 ? D.cy : D.cs)));
-    const double coff = (b == 0) ? D.offx : ((b == 2) ? D.offy : 0.0);
+    const T *src = static_cast<const T *>(b == 0 ? Dsrc.cx : (b == 1 ? Dsrc.cc : (b == 2 ? Dsrc.cy : Dsrc.cs)));
+    const double coff = (b == 0) ? offx : ((b == 2) ? offy : 0.0);
     double zz = 0.0;
     for (int j = kk; j < NV; ++j) zz += R[kk * NV + j] * (double(src[size_t(l) * NV + j]) - coff);
     vz[b * NVP + kk] = T(zz);
     // lambda_z = R^-T lambda
-    const T *glam = static_cast<const T *>(D.lam);
+    const T *glam = static_cast<const T *>(Dsrc.lam);
     double lz = 0.0;
     for (int j = 0; j <= kk; ++j) lz += Rinv[j * NV + kk] * double(glam[size_t(l) * 4 * NV + b * NV + j]);
     vlam[b * NVP + kk] = T(lz);
   } else if (lane < 5 * NV) {
     const int kk = lane - 4 * NV;
-    const T *H2 = static_cast<const T *>(D.H2);
+    const T *H2 = static_cast<const T *>(Dsrc.H2);
     double hsum = 0.0;
-    for (int e = 0; e < 6; ++e) hsum += double(H2[kk * 6 + e]) * D.bpsi[e];
+    for (int e = 0; e < 6; ++e) hsum += double(H2[kk * 6 + e]) * Dsrc.bpsi[e];
     vh[4 * NVP + kk] = T(hsum);
-    const T *src = static_cast<const T *>(D.cpsi);
+    const T *src = static_cast<const T *>(Dsrc.cpsi);
     double zz = 0.0;
     for (int j = kk; j < NV; ++j) zz += R[kk * NV + j] * double(src[size_t(l) * NV + j]);
     vzpsi[kk] = T(zz);
-    const T *glp = static_cast<const T *>(D.lampsi);
+    const T *glp = static_cast<const T *>(Dsrc.lampsi);
     double lz = 0.0;
     for (int j = 0; j <= kk; ++j) lz += Rinv[j * NV + kk] * double(glp[size_t(l) * NV + j]);
     vlampsi[kk] = T(lz);
   }
   wave_sync();
 
-  // ---- per-slot trajectory values
-  T x[kSlots], xd[kSlots], xdd[kSlots], cc[kSlots], y[kSlots], yd[kSlots], ydd[kSlots], ss[kSlots];
-  T psi[kSlots], cps[kSlots], sps[kSlots], psih[kSlots];
+  // ---- per-lane trajectory values at t
+  T x, xd, xdd, cc, y, yd, ydd, ss, psi, cps, sps, psih;
 
   auto eval_xy = [&]() {
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      T a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        const T zx = vz[k], zc = vz[NVP + k], zy = vz[2 * NVP + k], zs = vz[3 * NVP + k];
-        a0 += Ub[s][k] * zx; a1 += Vb[s][k] * zx; a2 += Wb[s][k] * zx; a3 += Ub[s][k] * zc;
-        b0 += Ub[s][k] * zy; b1 += Vb[s][k] * zy; b2 += Wb[s][k] * zy; b3 += Ub[s][k] * zs;
-      }
-      x[s] = a0; xd[s] = a1; xdd[s] = a2; cc[s] = a3;
-      y[s] = b0; yd[s] = b1; ydd[s] = b2; ss[s] = b3;
+    for (int k = 0; k < NV; ++k) {
+      const T zx = vz[k], zc = vz[NVP + k], zy = vz[2 * NVP + k], zs = vz[3 * NVP + k];
+      a0 += Ub[k] * zx; a1 += Vb[k] * zx; a2 += Wb[k] * zx; a3 += Ub[k] * zc;
+      b0 += Ub[k] * zy; b1 += Vb[k] * zy; b2 += Wb[k] * zy; b3 += Ub[k] * zs;
     }
+    x = a0; xd = a1; xdd = a2; cc = a3;
+    y = b0; yd = b1; ydd = b2; ss = b3;
   };
   auto eval_psi = [&]() {
+    T p = 0;
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      T p = 0;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) p += Ub[s][k] * vzpsi[k];
-      psi[s] = p;
-      T sn, cs;
-      Num<T>::sincos_(p, &sn, &cs);
-      cps[s] = cs;
-      sps[s] = sn;
-    }
+    for (int k = 0; k < NV; ++k) p += Ub[k] * vzpsi[k];
+    psi = p;
+    T sn, cs;
+    Num<T>::sincos_(p, &sn, &cs);
+    cps = cs;
+    sps = sn;
+  };
+
+  // Both waves' halves of one exchange group, added in a fixed order.
+  auto exchange_sum = [&](int g, int k) -> T {
+    return xch[g * kXchStride + k] + xch[XG_COUNT * kXchStride + g * kXchStride + k];
   };
 
   // ---- xi3/xi4 projection of every (circle, obstacle, t), velocity and
   // acceleration, then F^T (F xi - g) into vtr and U^T(psi - psi_hat) into
-  // vtpsi.
+  // vtpsi (both halves of t summed).
   auto project_reduce = [&](bool with_psi) {
+    const T ux = slack ? cc : cps, uy = slack ? ss : sps;
+    T Sx[kMaxC], Sy[kMaxC];
+#pragma unroll
+    for (int i = 0; i < kMaxC; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
+    if (!literal_alpha) {
+      // wave-wide vote: obstacles near enough to some lane's robot
+      const T ext = rmax * Num<T>::sqrt_(ux * ux + uy * uy);
+      uint64_t near_mask = 0;
+      for (int j = 0; j < n; ++j) {
+        const T dx = x - ox[j * q + tt], dy = y - oy[j * q + tt];
+        const T reach = ext + op[j * 8 + OP_AMAX];
+        const bool near = tv && (dx * dx + dy * dy < reach * reach);
+        if (__any(near)) near_mask |= uint64_t(1) << j;
+      }
+      while (near_mask) {
+        const int j = __builtin_ctzll(near_mask);
+        near_mask &= near_mask - 1;
+        const T oxj = ox[j * q + tt], oyj = oy[j * q + tt];
+        const T a2 = op[j * 8 + OP_A2], b2 = op[j * 8 + OP_B2], ab = op[j * 8 + OP_AB];
+#pragma unroll
+        for (int i = 0; i < kMaxC; ++i) {
+          if (i < m) {
+            const T xt = x + rr[i] * ux - oxj, yt = y + rr[i] * uy - oyj;
+            const T r2 = b2 * xt * xt + a2 * yt * yt;
+            const T f1 = fmax(T(0), ab * Num<T>::rsqrt(r2) - T(1));
+            Sx[i] += xt * f1;
+            Sy[i] += yt * f1;
+          }
+        }
+      }
+    } else {
+      for (int j = 0; j < n; ++j) {
+        const T oxj = ox[j * q + tt], oyj = oy[j * q + tt];
+        const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
+        const T a2 = op[j * 8 + OP_A2], b2 = op[j * 8 + OP_B2];
+#pragma unroll
+        for (int i = 0; i < kMaxC; ++i) {
+          if (i < m) {
+            const T xt = x + rr[i] * ux - oxj, yt = y + rr[i] * uy - oyj;
+            const T xx = xt * xt, yy = yt * yt;
+            const T kap = fmax(Num<T>::rsqrt(xx + yy), (a * xx + b * yy) / (a2 * xx + b2 * yy));
+            Sx[i] += xt * (a * kap - T(1));
+            Sy[i] += yt * (b * kap - T(1));
+          }
+        }
+      }
+    }
+    // Exact zero (or underflowed) offsets make the fast form non-finite;
+    // redo those sums element by element (alpha := 0 at the zero vector).
+#pragma unroll
+    for (int i = 0; i < kMaxC; ++i) {
+      if (i < m && !(isfinite(Sx[i]) && isfinite(Sy[i]))) {
+        T sx = T(0), sy = T(0);
+        for (int j = 0; j < n; ++j) {
+          const T xt = x + rr[i] * ux - ox[j * q + tt], yt = y + rr[i] * uy - oy[j * q + tt];
+          const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
+          if (xt == T(0) && yt == T(0)) {
+            sx += a;   // alpha = 0, d = 1: target (x_j + a, y_j)
+          } else if (!literal_alpha) {
+            const T rr_ = Num<T>::hypot_(b * xt, a * yt);
+            const T f1 = fmax(T(0), (a * b) / rr_ - T(1));
+            sx += xt * f1;
+            sy += yt * f1;
+          } else {
+            const T rho0 = Num<T>::hypot_(xt, yt);
+            const T ca = xt / rho0, sa = yt / rho0;
+            const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
+            sx += a * dd * ca - xt;
+            sy += b * dd * sa - yt;
+          }
+        }
+        Sx[i] = sx;
+        Sy[i] = sy;
+      }
+    }
+    T Dx = 0, Dy = 0, DRx = 0, DRy = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxC; ++i) {
+      Dx += Sx[i]; Dy += Sy[i];
+      DRx += rr[i] * Sx[i]; DRy += rr[i] * Sy[i];
+    }
+    // velocity / acceleration: part of (xdot, ydot) outside the disc
+    const T fv = fmax(T(0), T(1) - vmax * Num<T>::rsqrt(xd * xd + yd * yd));
+    const T fa = fmax(T(0), T(1) - amax * Num<T>::rsqrt(xdd * xdd + ydd * ydd));
+    const T rvx = xd * fv, rvy = yd * fv, rax = xdd * fa, ray = ydd * fa;
+    const T dc = cc - cps, ds = ss - sps;
+    const T k1 = slack ? T(0) : s1, k2 = (slack ? T(0) : s2) + T(1);
+    const T ro1x = k1 * dc - Dx, ro2x = k2 * dc - DRx;
+    const T ro1y = k1 * ds - Dy, ro2y = k2 * ds - DRy;
+    const T rp = psi_sign * (psi - psih);
     T p1x[NV], p2x[NV], p1y[NV], p2y[NV], pps[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) p1x[k] = p2x[k] = p1y[k] = p2y[k] = pps[k] = T(0);
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      if (!tv[s]) continue;
-      const int t = lane + kWave * s;
-      const T ux = slack ? cc[s] : cps[s], uy = slack ? ss[s] : sps[s];
-      T Xi[kMaxC], Yi[kMaxC], Sx[kMaxC], Sy[kMaxC];
-#pragma unroll
-      for (int i = 0; i < kMaxC; ++i) {
-        Xi[i] = x[s] + rr[i] * ux;
-        Yi[i] = y[s] + rr[i] * uy;
-        Sx[i] = T(0);
-        Sy[i] = T(0);
-      }
-      if (!literal_alpha) {
-        for (int j = 0; j < n; ++j) {
-          const T oxj = ox[j * q + t], oyj = oy[j * q + t];
-          const T a2 = op[j * 8 + OP_A2], b2 = op[j * 8 + OP_B2], ab = op[j * 8 + OP_AB];
-#pragma unroll
-          for (int i = 0; i < kMaxC; ++i) {
-            if (i < m) {
-              const T xt = Xi[i] - oxj, yt = Yi[i] - oyj;
-              const T r2 = b2 * xt * xt + a2 * yt * yt;
-              const T f1 = fmax(T(0), ab * Num<T>::rsqrt(r2) - T(1));
-              Sx[i] += xt * f1;
-              Sy[i] += yt * f1;
-            }
-          }
-        }
-      } else {
-        for (int j = 0; j < n; ++j) {
-          const T oxj = ox[j * q + t], oyj = oy[j * q + t];
-          const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
-          const T a2 = op[j * 8 + OP_A2], b2 = op[j * 8 + OP_B2];
-#pragma unroll
-          for (int i = 0; i < kMaxC; ++i) {
-            if (i < m) {
-              const T xt = Xi[i] - oxj, yt = Yi[i] - oyj;
-              const T xx = xt * xt, yy = yt * yt;
-              const T kap = fmax(Num<T>::rsqrt(xx + yy), (a * xx + b * yy) / (a2 * xx + b2 * yy));
-              Sx[i] += xt * (a * kap - T(1));
-              Sy[i] += yt * (b * kap - T(1));
-            }
-          }
-        }
-      }
-      // Exact zero (or underflowed) offsets make the fast form non-finite;
-      // redo those sums element by element (alpha := 0 at the zero vector).
-#pragma unroll
-      for (int i = 0; i < kMaxC; ++i) {
-        if (i < m && !(isfinite(Sx[i]) && isfinite(Sy[i]))) {
-          T sx = T(0), sy = T(0);
-          for (int j = 0; j < n; ++j) {
-            const T xt = Xi[i] - ox[j * q + t], yt = Yi[i] - oy[j * q + t];
-            const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
-            if (xt == T(0) && yt == T(0)) {
-              sx += a;   // alpha = 0, d = 1: target (x_j + a, y_j)
-            } else if (!literal_alpha) {
-              const T rr_ = Num<T>::hypot_(b * xt, a * yt);
-              const T f1 = fmax(T(0), (a * b) / rr_ - T(1));
-              sx += xt * f1;
-              sy += yt * f1;
-            } else {
-              const T rho0 = Num<T>::hypot_(xt, yt);
-              const T ca = xt / rho0, sa = yt / rho0;
-              const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
-              sx += a * dd * ca - xt;
-              sy += b * dd * sa - yt;
-            }
-          }
-          Sx[i] = sx;
-          Sy[i] = sy;
-        }
-      }
-      T Dx = 0, Dy = 0, DRx = 0, DRy = 0;
-#pragma unroll
-      for (int i = 0; i < kMaxC; ++i) {
-        Dx += Sx[i]; Dy += Sy[i];
-        DRx += rr[i] * Sx[i]; DRy += rr[i] * Sy[i];
-      }
-      // velocity / acceleration: part of (xdot, ydot) outside the disc
-      const T fv = fmax(T(0), T(1) - vmax * Num<T>::rsqrt(xd[s] * xd[s] + yd[s] * yd[s]));
-      const T fa = fmax(T(0), T(1) - amax * Num<T>::rsqrt(xdd[s] * xdd[s] + ydd[s] * ydd[s]));
-      const T rvx = xd[s] * fv, rvy = yd[s] * fv, rax = xdd[s] * fa, ray = ydd[s] * fa;
-      const T dc = cc[s] - cps[s], ds = ss[s] - sps[s];
-      const T k1 = slack ? T(0) : s1, k2 = (slack ? T(0) : s2) + T(1);
-      const T ro1x = k1 * dc - Dx, ro2x = k2 * dc - DRx;
-      const T ro1y = k1 * ds - Dy, ro2y = k2 * ds - DRy;
-      const T rp = psi_sign * (psi[s] - psih[s]);
-#pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        p1x[k] += Vb[s][k] * rvx + Wb[s][k] * rax + Ub[s][k] * ro1x;
-        p2x[k] += Ub[s][k] * ro2x;
-        p1y[k] += Vb[s][k] * rvy + Wb[s][k] * ray + Ub[s][k] * ro1y;
-        p2y[k] += Ub[s][k] * ro2y;
-        pps[k] += Ub[s][k] * rp;
-      }
+    for (int k = 0; k < NV; ++k) {
+      p1x[k] = Vb[k] * rvx + Wb[k] * rax + Ub[k] * ro1x;
+      p2x[k] = Ub[k] * ro2x;
+      p1y[k] = Vb[k] * rvy + Wb[k] * ray + Ub[k] * ro1y;
+      p2y[k] = Ub[k] * ro2y;
+      pps[k] = Ub[k] * rp;
     }
     const T r0 = wave_sum_rows<T, NV>(p1x, red, lane);
     const T r1 = wave_sum_rows<T, NV>(p2x, red, lane);
     const T r2 = wave_sum_rows<T, NV>(p1y, red, lane);
     const T r3 = wave_sum_rows<T, NV>(p2y, red, lane);
+    T r4 = T(0);
+    if (with_psi) r4 = wave_sum_rows<T, NV>(pps, red, lane);
     if (lane < NV) {
-      vtr[lane] = r0;
-      vtr[NVP + lane] = r1;
-      vtr[2 * NVP + lane] = r2;
-      vtr[3 * NVP + lane] = r3;
+      xmine[XG_T1X * kXchStride + lane] = r0;
+      xmine[XG_T2X * kXchStride + lane] = r1;
+      xmine[XG_T1Y * kXchStride + lane] = r2;
+      xmine[XG_T2Y * kXchStride + lane] = r3;
+      xmine[XG_TPSI * kXchStride + lane] = r4;
     }
-    if (with_psi) {
-      const T r4 = wave_sum_rows<T, NV>(pps, red, lane);
-      if (lane < NV) vtpsi[lane] = r4;
+    __syncthreads();
+    if (lane < NV) {
+      vtr[lane] = exchange_sum(XG_T1X, lane);
+      vtr[NVP + lane] = exchange_sum(XG_T2X, lane);
+      vtr[2 * NVP + lane] = exchange_sum(XG_T1Y, lane);
+      vtr[3 * NVP + lane] = exchange_sum(XG_T2Y, lane);
+      vtpsi[lane] = exchange_sum(XG_TPSI, lane);
     }
     wave_sync();
   };
@@ -316,8 +325,7 @@ __device__ void fused_body(const Desc &D, int l, T *lds, const FusedLds &L, int 
   // ---- step 1 of the AM list: initial xi3, xi4 from the given trajectory
   eval_xy();
   eval_psi();
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s) psih[s] = psi[s];
+  psih = psi;
   project_reduce(false);
   if (lane < 4 * NV) {
     const T v = next_rhs(lane);
@@ -325,7 +333,7 @@ __device__ void fused_body(const Desc &D, int l, T *lds, const FusedLds &L, int 
   }
   wave_sync();
 
-  for (int it = 0; it < D.K; ++it) {
+  for (int it = 0; it < K; ++it) {
     // ---- xi1: [z; mu] = KKT^-1 [lambda + rho F^T g; b]  (eqs. over_3, zeta_1_sepration_3)
     if (lane < 4 * NV) {
       const int b = lane / NV, kk = lane % NV, axis = b >> 1;
@@ -341,22 +349,19 @@ __device__ void fused_body(const Desc &D, int l, T *lds, const FusedLds &L, int 
 
     // ---- xi2: psi_hat = atan2(s, c) on the branch nearest psi^k, then the
     // heading QP (eq. compute_convex_surrogate)
+    {
+      T ph;
+      if (unwrap) ph = psi + atan2z(ss * cps - cc * sps, cc * cps + ss * sps);
+      else ph = atan2z(ss, cc);
+      psih = tv ? ph : T(0);
+    }
     T pp[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) pp[k] = T(0);
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      T ph;
-      if (unwrap)
-        ph = psi[s] + atan2z(ss[s] * cps[s] - cc[s] * sps[s], cc[s] * cps[s] + ss[s] * sps[s]);
-      else
-        ph = atan2z(ss[s], cc[s]);
-      psih[s] = tv[s] ? ph : T(0);
-#pragma unroll
-      for (int k = 0; k < NV; ++k) pp[k] += Ub[s][k] * psih[s];
-    }
+    for (int k = 0; k < NV; ++k) pp[k] = Ub[k] * psih;
     const T upsi = wave_sum_rows<T, NV>(pp, red, lane);
-    if (lane < NV) vtmp[lane] = vlampsi[lane] + rho * upsi;
+    if (lane < NV) xmine[XG_PSIH * kXchStride + lane] = upsi;
+    __syncthreads();
+    if (lane < NV) vtmp[lane] = vlampsi[lane] + rho * exchange_sum(XG_PSIH, lane);
     wave_sync();
     if (lane < NV) {
       T acc = vh[4 * NVP + lane];
@@ -384,73 +389,63 @@ __device__ void fused_body(const Desc &D, int l, T *lds, const FusedLds &L, int 
     wave_sync();
   }
 
-  // ---- state back to Bernstein coordinates
-  if (lane < 4 * NV) {
-    const int b = lane / NV, kk = lane % NV;
-    T *dst = static_cast<T *>(b == 0 ? D.cx : (b == 1 ? D.cc : (b == 2 ? D.cy : D.cs)));
-    const double coff = (b == 0) ? D.offx : ((b == 2) ? D.offy : 0.0);
-    double c = 0.0, lc = 0.0;
-    for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * double(vz[b * NVP + j]);
-    for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(vlam[b * NVP + j]);
-    dst[size_t(l) * NV + kk] = T(c + coff);
-    static_cast<T *>(D.lam)[size_t(l) * 4 * NV + b * NV + kk] = T(lc);
-  } else if (lane < 5 * NV) {
-    const int kk = lane - 4 * NV;
-    double c = 0.0, lc = 0.0;
-    for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * double(vzpsi[j]);
-    for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(vlampsi[j]);
-    static_cast<T *>(D.cpsi)[size_t(l) * NV + kk] = T(c);
-    static_cast<T *>(D.lampsi)[size_t(l) * NV + kk] = T(lc);
+  if (!live) return;   // padding trajectory of a ragged last block
+
+  // ---- state back to Bernstein coordinates (written by the first half)
+  if (half == 0) {
+    if (lane < 4 * NV) {
+      const int b = lane / NV, kk = lane % NV;
+      T *dst = static_cast<T *>(b == 0 ? Dsrc.cx : (b == 1 ? Dsrc.cc : (b == 2 ? Dsrc.cy : Dsrc.cs)));
+      const double coff = (b == 0) ? offx : ((b == 2) ? offy : 0.0);
+      double c = 0.0, lc = 0.0;
+      for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * double(vz[b * NVP + j]);
+      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(vlam[b * NVP + j]);
+      dst[size_t(l) * NV + kk] = T(c + coff);
+      static_cast<T *>(Dsrc.lam)[size_t(l) * 4 * NV + b * NV + kk] = T(lc);
+    } else if (lane < 5 * NV) {
+      const int kk = lane - 4 * NV;
+      double c = 0.0, lc = 0.0;
+      for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * double(vzpsi[j]);
+      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(vlampsi[j]);
+      static_cast<T *>(Dsrc.cpsi)[size_t(l) * NV + kk] = T(c);
+      static_cast<T *>(Dsrc.lampsi)[size_t(l) * NV + kk] = T(lc);
+    }
   }
+  if (!tv) return;
 
   // ---- optional outputs: trajectory and the final (alpha, d) of xi3/xi4
-  if (D.traj) {
-    T *tr = static_cast<T *>(D.traj) + size_t(l) * 3 * q;
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s)
-      if (tv[s]) {
-        const int t = lane + kWave * s;
-        tr[t] = x[s] + T(D.offx);
-        tr[q + t] = y[s] + T(D.offy);
-        tr[2 * q + t] = psi[s];
-      }
+  if (Dsrc.traj) {
+    T *tr = static_cast<T *>(Dsrc.traj) + size_t(l) * 3 * q;
+    tr[t] = x + T(offx);
+    tr[q + t] = y + T(offy);
+    tr[2 * q + t] = psi;
   }
-  if (D.va) {
-    T *va = static_cast<T *>(D.va) + size_t(l) * 4 * q;
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s)
-      if (tv[s]) {
-        const int t = lane + kWave * s;
-        const T av = atan2z(yd[s], xd[s]), aa = atan2z(ydd[s], xdd[s]);
-        const T dv = (xd[s] * Num<T>::cos_(av) + yd[s] * Num<T>::sin_(av)) / vmax;
-        const T da = (xdd[s] * Num<T>::cos_(aa) + ydd[s] * Num<T>::sin_(aa)) / amax;
-        va[t] = av;
-        va[q + t] = fmin(T(1), fmax(T(0), dv));
-        va[2 * q + t] = aa;
-        va[3 * q + t] = fmin(T(1), fmax(T(0), da));
-      }
+  if (Dsrc.va) {
+    T *va = static_cast<T *>(Dsrc.va) + size_t(l) * 4 * q;
+    const T av = atan2z(yd, xd), aa = atan2z(ydd, xdd);
+    const T dv = (xd * Num<T>::cos_(av) + yd * Num<T>::sin_(av)) / vmax;
+    const T da = (xdd * Num<T>::cos_(aa) + ydd * Num<T>::sin_(aa)) / amax;
+    va[t] = av;
+    va[q + t] = fmin(T(1), fmax(T(0), dv));
+    va[2 * q + t] = aa;
+    va[3 * q + t] = fmin(T(1), fmax(T(0), da));
   }
-  if (D.alpha || D.d) {
-    T *ga = static_cast<T *>(D.alpha), *gd = static_cast<T *>(D.d);
+  if (Dsrc.alpha || Dsrc.d) {
+    T *ga = static_cast<T *>(Dsrc.alpha), *gd = static_cast<T *>(Dsrc.d);
     const size_t base = size_t(l) * m * n * q;
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      if (!tv[s]) continue;
-      const int t = lane + kWave * s;
-      const T ux = slack ? cc[s] : cps[s], uy = slack ? ss[s] : sps[s];
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < n; ++j) {
-          const T xt = x[s] + rr[i] * ux - ox[j * q + t];
-          const T yt = y[s] + rr[i] * uy - oy[j * q + t];
-          const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
-          const T al = literal_alpha ? atan2z(yt, xt) : atan2z(a * yt, b * xt);
-          const T ca = Num<T>::cos_(al), sa = Num<T>::sin_(al);
-          const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
-          const size_t e = base + size_t(i * n + j) * q + t;
-          if (ga) ga[e] = al;
-          if (gd) gd[e] = dd;
-        }
-    }
+    const T ux = slack ? cc : cps, uy = slack ? ss : sps;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < n; ++j) {
+        const T xt = x + rr[i] * ux - ox[j * q + t];
+        const T yt = y + rr[i] * uy - oy[j * q + t];
+        const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
+        const T al = literal_alpha ? atan2z(yt, xt) : atan2z(a * yt, b * xt);
+        const T ca = Num<T>::cos_(al), sa = Num<T>::sin_(al);
+        const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
+        const size_t e = base + size_t(i * n + j) * q + t;
+        if (ga) ga[e] = al;
+        if (gd) gd[e] = dd;
+      }
   }
 }
 
@@ -470,21 +465,22 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void fused_kernel(Desc singl
   }
   const Desc &D = table ? table[p] : single;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const int q = D.q, n = D.n;
+  const int q = D.q, n = D.n, B = D.B, blk0 = D.blk0;
   const FusedLds L = fused_layout(q, n, NV);
 
   // block-wide: obstacle tables (centred), inflated semi-axes, operators
   const T *gox = static_cast<const T *>(D.ox), *goy = static_cast<const T *>(D.oy);
-  const T offx = T(D.offx), offy = T(D.offy);
+  const T offx = T(D.offx), offy = T(D.offy), rc = T(D.rc);
   for (int i = tid; i < n * q; i += blockDim.x) {
     lds[L.ox + i] = gox[i] - offx;
     lds[L.oy + i] = goy[i] - offy;
   }
   for (int j = tid; j < n; j += blockDim.x) {
-    const T a = static_cast<const T *>(D.oa)[j] + T(D.rc);
-    const T b = static_cast<const T *>(D.ob)[j] + T(D.rc);
+    const T a = static_cast<const T *>(D.oa)[j] + rc;
+    const T b = static_cast<const T *>(D.ob)[j] + rc;
     T *o = lds + L.op + j * 8;
     o[OP_A] = a; o[OP_B] = b; o[OP_A2] = a * a; o[OP_B2] = b * b; o[OP_AB] = a * b;
+    o[OP_AMAX] = fmax(a, b);
   }
   const T *gM1 = static_cast<const T *>(D.M1), *gM2 = static_cast<const T *>(D.M2),
           *gGF = static_cast<const T *>(D.GF);
@@ -495,9 +491,12 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void fused_kernel(Desc singl
   for (int i = tid; i < NV * NV; i += blockDim.x) lds[L.m2 + i] = gM2[i];
   __syncthreads();
 
-  const int l = (int(blockIdx.x) - D.blk0) * kWavesPerBlock + wave;
-  if (l >= D.B) return;   // no block-wide barrier follows
-  fused_body<T, NV>(D, l, lds, L, lane, wave);
+  // Both trajectories of the block run the loop (it has block-wide
+  // barriers); a slot past the end of the batch computes a copy of the last
+  // trajectory and stores nothing.
+  const int lt = (int(blockIdx.x) - blk0) * kTrajPerBlock + (wave >> 1);
+  const bool live = lt < B;
+  fused_body<T, NV>(D, live ? lt : B - 1, live, wave & 1, lds, L, lane, wave);
 }
 
 template <typename T, int NV>

@@ -10,8 +10,8 @@
 namespace amk {
 
 constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kWavesPerBlock = 4;  // fused kernel: one trajectory per wave
-constexpr int kSlots = 2;          // time slots per lane: t = lane + 64*s
+constexpr int kWavesPerBlock = 4;  // 256-thread blocks
+constexpr int kTrajPerBlock = 2;   // fused kernel: two wavefronts per trajectory
 constexpr int kRedStride = 68;     // LDS row stride of the reduction scratch
 
 // One problem of a launch: handle constants, problem data, state, sizes.
@@ -66,5 +66,11 @@ hipError_t launch_residuals(const Desc &d, const void *P, const void *Pd, const 
 hipError_t launch_desc_copy(const Desc *host_descs, int count, Desc *dev_dst, hipStream_t st);
 hipError_t launch_plain(const Desc &d, void *ws, size_t ws_bytes, bool f64, int nv, hipStream_t st);
 size_t plain_workspace_bytes(int B, int q, int nv, int m, int n, bool f64);
+
+// Shape of a handle (for the server).
+int handle_q(const am_handle *h);
+int handle_nv(const am_handle *h);
+int handle_n(const am_handle *h);
+int handle_dtype(const am_handle *h);
 
 }  // namespace amk

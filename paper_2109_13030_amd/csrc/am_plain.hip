@@ -234,7 +234,7 @@ __global__ void k_targets(Desc D, Ptrs<T> w) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= D.B * D.q) return;
   const int l = g / D.q, t = g % D.q, q = D.q, m = D.m, n = D.n;
-  const bool slack = D.flags & AM_XTILDE_SLACK;
+  const bool slack = D.flags & AM_XTILDE_SLACK, literal = D.flags & AM_ALPHA_LITERAL;
   const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
   const T x = tr[t], c = tr[3 * q + t], y = tr[4 * q + t], s = tr[7 * q + t];
   const T cp = p3[q + t], sp = p3[2 * q + t];
@@ -249,11 +249,16 @@ __global__ void k_targets(Desc D, Ptrs<T> w) {
       const T a = static_cast<const T *>(D.oa)[j] + T(D.rc), b = static_cast<const T *>(D.ob)[j] + T(D.rc);
       const T oxj = static_cast<const T *>(D.ox)[j * q + t] - T(D.offx);
       const T oyj = static_cast<const T *>(D.oy)[j * q + t] - T(D.offy);
-      T sa, ca;
-      Num<T>::sincos_(al[e], &sa, &ca);
-      // deviation of the target g from the current circle centre
-      sx += oxj + a * dd[e] * ca - (x + ri * ux);
-      sy += oyj + b * dd[e] * sa - (y + ri * uy);
+      // deviation of the target g from the current circle centre.  Under
+      // the elliptic angle a point with d > 1 lies outside the ellipse and
+      // is its own target (eqs. zeta_2, compute_zeta_3), so the deviation is
+      // exactly zero; the literal angle has no such fixed points.
+      if (literal || dd[e] <= T(1)) {
+        T sa, ca;
+        Num<T>::sincos_(al[e], &sa, &ca);
+        sx += a * dd[e] * ca - (x + ri * ux - oxj);
+        sy += b * dd[e] * sa - (y + ri * uy - oyj);
+      }
     }
     Dx += sx; Dy += sy; DRx += ri * sx; DRy += ri * sy;
   }
@@ -269,12 +274,14 @@ __global__ void k_targets(Desc D, Ptrs<T> w) {
   const T dc = c - cp, ds = s - sp;
   const T k1 = slack ? T(0) : s1, k2 = (slack ? T(0) : s2) + T(1);
   T *ch = w.chan + size_t(l) * 9 * q + t;
-  ch[0] = tr[q + t] - vm * va[q + t] * cv;          // xdot - g_v
-  ch[q] = tr[2 * q + t] - am * va[3 * q + t] * ca;  // xddot - g_a
+  // inside the disc (d_v < 1) the velocity is its own target
+  const bool vin = va[q + t] < T(1), ain = va[3 * q + t] < T(1);
+  ch[0] = vin ? T(0) : tr[q + t] - vm * va[q + t] * cv;          // xdot - g_v
+  ch[q] = ain ? T(0) : tr[2 * q + t] - am * va[3 * q + t] * ca;  // xddot - g_a
   ch[2 * q] = k1 * dc - Dx;                         // sum_ij (x + r_i c - g_ob)
   ch[3 * q] = k2 * dc - DRx;                        // sum_ij r_i (...) + (c - cos psi)
-  ch[4 * q] = tr[5 * q + t] - vm * va[q + t] * sv;
-  ch[5 * q] = tr[6 * q + t] - am * va[3 * q + t] * sa;
+  ch[4 * q] = vin ? T(0) : tr[5 * q + t] - vm * va[q + t] * sv;
+  ch[5 * q] = ain ? T(0) : tr[6 * q + t] - am * va[3 * q + t] * sa;
   ch[6 * q] = k1 * ds - Dy;
   ch[7 * q] = k2 * ds - DRy;
   const T psi_sign = (D.flags & AM_LAMPSI_LITERAL) ? T(-1) : T(1);

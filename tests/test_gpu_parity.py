@@ -47,8 +47,23 @@ def test_setup_inverse_matches_oracle_kkt(name):
 
 # ------------------------------------------------------------- FP64 GPU = oracle (same algorithm)
 
-def _compare_f64(pb, init, K, tol=1e-8, projections=True):
-    h, p, st = H.run_gpu(pb, init, K, "f64", projections=projections)
+def _run_plain(pb, init, K, dtype, projections=True):
+    import torch
+    from paper_2109_13030_amd import am
+    h = am.Handle.for_problem(pb, dtype)
+    p = am.DeviceProblem(pb, dtype)
+    st = am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], dtype=dtype, projections=projections)
+    ws = torch.empty(am.plain_workspace_size(h, st.B), dtype=torch.uint8, device="cuda")
+    am.solve_plain(h, p, st, K, ws)
+    torch.cuda.synchronize()
+    return h, p, st
+
+
+def _compare_f64(pb, init, K, tol=1e-8, projections=True, plain=False):
+    if plain:
+        h, p, st = _run_plain(pb, init, K, "f64", projections=projections)
+    else:
+        h, p, st = H.run_gpu(pb, init, K, "f64", projections=projections)
     out = st.numpy()
     orc, ost = H.run_oracle(pb, init, K)
     epos, epsi = H.traj_errors(pb, out, orc, ost)
@@ -203,3 +218,28 @@ def test_multi_problem_launch_equals_single_launches():
     for s, s1 in zip(sts, singles):
         for k in ("cx", "cy", "cpsi", "lam", "lam_psi", "traj"):
             assert torch.equal(s.t[k], s1.t[k]), k
+
+
+# ------------------------------------------------------------- plain path (one launch per sub-step)
+
+def test_plain_f64_matches_oracle():
+    """The per-sub-step path with alpha, d in device memory gives the oracle's
+    result (FP64, c1, 30 iterations)."""
+    pb, init = inputs.workload("c1", batch=7)
+    _compare_f64(pb, init, 30, plain=True)
+
+
+@pytest.mark.parametrize("flags", [oracle.ALPHA_LITERAL, oracle.XTILDE_SLACK, oracle.LAMPSI_LITERAL])
+def test_plain_readings_f64(flags):
+    pb, init = inputs.workload("c2", batch=5)
+    _compare_f64(dict(pb, flags=flags), init, 6, plain=True)
+
+
+def test_plain_f32_c2_sampled_against_oracle():
+    """Plain path at the full c2 size, sampled against the oracle."""
+    pb, init = inputs.workload("c2")
+    _, _, st = _run_plain(pb, init, 100, "f32", projections=False)
+    out = st.numpy()
+    B = out["cx"].shape[0]
+    idx = np.unique(np.concatenate([[0, B - 1], np.random.default_rng(1).choice(B, 22, replace=False)]))
+    _fp32_gate(pb, init, 100, idx, out)
