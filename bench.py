@@ -167,7 +167,203 @@ def run_gpu(args):
                         "launches_per_step": 6 * K + 7,
                         "fused_speedup": value / pvalue,
                         "hbm_bytes_per_iteration": plain_bytes_per_iter(q, nv, m, n, B)}
+    out["_final"] = last.numpy()
     return out, pb, init, K
+
+
+def run_serving(rates, n_requests: int, modes=("continuous", "plain"), n_clients: int = 32,
+                saturation: int = 64, budget: int = 4 << 30, seed: int = 5):
+    """Replanning workload c5 through the continuous-batching server: Poisson
+    arrivals, per request B ~ U{256..2048}, n ~ U{5..30} moving obstacles,
+    5 circles, 20 warm-started AM iterations.  Latency = completion seen by
+    the server's scheduler - submission.  Also a saturation run (all
+    requests submitted at once) for capacity."""
+    import torch
+
+    from paper_2109_13030_amd import am, inputs
+
+    torch.cuda.set_device(0)
+    cfg = inputs.CONFIGS["c5"]
+    K = cfg.iters
+    clients = inputs.serving_clients(n_clients)
+    handles = {}
+    for c in clients:
+        if c["n"] not in handles:
+            handles[c["n"]] = am.Handle.for_problem(c["problem"], "f32")
+    mode_ids = {"continuous": am.SERVE_CONTINUOUS, "sequential": am.SERVE_SEQUENTIAL, "plain": am.SERVE_PLAIN}
+    out = {"workload": "c5: Poisson replanning requests, B ~ U{256..2048}, n ~ U{5..30} moving obstacles, "
+                       f"5 circles, {K} warm-started AM iterations per request, {n_clients} robots",
+           "iterations": K, "requests_per_rate": n_requests, "budget_bytes": budget, "modes": {}}
+
+    def one(mode, rate, count, rseed):
+        srv = am.Server(budget, streams=4, max_per_launch=64, mode=mode_ids[mode])
+        rng = np.random.default_rng(rseed)
+        steps = [0] * len(clients)
+        # every robot's first (cold) request is served before the timed run
+        first = [srv.submit(handles[c["n"]], c["problem"], i, c["batch"], K, c["init"])
+                 for i, c in enumerate(clients)]
+        for t in first:
+            if not srv.wait(t, 120.0)[0]:
+                raise RuntimeError("a serving request did not finish within 120 s")
+        arr = inputs.poisson_arrivals(rate, count, rseed) if rate else np.zeros(count)
+        work, tickets = 0, []
+        t0 = time.perf_counter()
+        for ta in arr:
+            while True:
+                now = time.perf_counter() - t0
+                if now >= ta:
+                    break
+                time.sleep(min(ta - now, 2e-4))
+            i = int(rng.integers(len(clients)))
+            c = clients[i]
+            steps[i] += 1
+            pb = inputs.replan_problem(c["problem"], steps[i])
+            init = inputs.make_initial(pb, c["batch"], int(rng.integers(1 << 31)), cfg.sigma)
+            tickets.append(srv.submit(handles[c["n"]], pb, i, c["batch"], K, init))
+            work += c["batch"] * K
+        lat = []
+        for t in tickets:
+            done, l, _ = srv.wait(t, 120.0)
+            if not done:
+                raise RuntimeError("a serving request did not finish within 120 s")
+            lat.append(l)
+        lat = np.array(lat)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return {"rate_hz": rate, "requests": count, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+                "max_ms": float(lat.max() * 1e3), "traj_iter_per_s": work / wall,
+                "launches": st["launches"] - len(clients), "memory_waits": st["memory_waits"],
+                "peak_bytes": st["peak_bytes"]}
+
+    for mode in modes:
+        rows = [one(mode, r, n_requests, seed + int(r)) for r in rates]
+        if saturation:
+            rows.append(one(mode, 0, saturation, seed))
+        out["modes"][mode] = rows
+    return out
+
+
+def run_uneven(reps: int = 3, count: int | None = None):
+    """Uneven multi-problem workload c3: 64 independent problems (B ~
+    U{64..1024}, 3-5 circles, 2-20 obstacles, K = 100) solved (a) one problem
+    at a time on the plain path, (b) one fused launch per problem, (c) all in
+    one multi-problem launch, (d) that launch captured in a HIP graph and
+    replayed.  Returns trajectory-iterations per second of each."""
+    import torch
+
+    from paper_2109_13030_amd import am, inputs
+
+    torch.cuda.set_device(0)
+    cfg = inputs.CONFIGS["c3"]
+    K = cfg.iters
+    probs = inputs.uneven_problems("c3", count=count)
+    hs = [am.Handle.for_problem(pb, "f32") for pb, _ in probs]
+    dps = [am.DeviceProblem(pb, "f32") for pb, _ in probs]
+    mk = lambda: [am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32") for pb, init in probs]
+    work = sum(init["cx"].shape[0] for _, init in probs) * K
+    stream = torch.cuda.current_stream()
+
+    def timeit(fn, reps_):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps_):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps_ * 1e-3
+
+    out = {"workload": f"c3: {len(probs)} problems, batch U{{64..1024}} (total {work // K}), 3-5 circles, "
+                       f"2-20 moving obstacles, {K} iterations", "traj_iter_per_launch": work}
+    sts = mk()
+    wss = [torch.empty(am.plain_workspace_size(h, s_.B), dtype=torch.uint8, device="cuda") for h, s_ in zip(hs, sts)]
+    t = timeit(lambda: [am.solve_plain(h, p, s_, K, w) for h, p, s_, w in zip(hs, dps, sts, wss)], 1)
+    out["plain_per_problem"] = {"s": t, "traj_iter_per_s": work / t}
+    del wss
+    t = timeit(lambda: [am.solve(h, p, s_, K) for h, p, s_ in zip(hs, dps, sts)], reps)
+    out["fused_per_problem"] = {"s": t, "traj_iter_per_s": work / t}
+    ws = torch.empty(am.multi_workspace_size(len(probs)), dtype=torch.uint8, device="cuda")
+    t = timeit(lambda: am.solve_multi(hs, dps, sts, K, ws), reps)
+    out["one_launch"] = {"s": t, "traj_iter_per_s": work / t}
+    best, times = am.autotune_multi(hs, dps, mk(), K, ws)
+    out["autotune"] = {"best_tile": best, "ms_per_tile": {str(k): v for k, v in times.items()}}
+    t = timeit(lambda: am.solve_multi(hs, dps, sts, K, ws), reps)
+    out["one_launch_tuned"] = {"s": t, "traj_iter_per_s": work / t, "tile": best}
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        am.solve_multi(hs, dps, sts, K, ws)
+    t = timeit(g.replay, reps)
+    out["one_launch_graph"] = {"s": t, "traj_iter_per_s": work / t, "tile": best}
+    out["speedup_one_launch_vs_plain"] = out["one_launch"]["traj_iter_per_s"] / out["plain_per_problem"]["traj_iter_per_s"]
+    return out
+
+
+def run_precision(sample: int = 24, steps: int = 3):
+    """Precision workload c4 (B = 4096, 5 circles, 20 moving obstacles,
+    K = 100): the one-launch FP32 solve, the plain FP32 path and the plain
+    path with the BF16 split contraction, each timed and compared with the
+    FP64 oracle on a sample of trajectories (max |dx|, |dy| in m and |dpsi|
+    in rad; trajectories whose FP64 result moves by more than 5e-5 under a
+    2^-24 perturbation of their inputs are reported separately)."""
+    import torch
+
+    import oracle
+    from paper_2109_13030_amd import am, inputs
+
+    torch.cuda.set_device(0)
+    pb, init = inputs.workload("c4")
+    K = inputs.CONFIGS["c4"].iters
+    B, m, n, q = init["cx"].shape[0], len(pb["r"]), len(pb["oa"]), pb["q"]
+    idx = np.unique(np.linspace(0, B - 1, sample).astype(int))
+    sub = {k: np.asarray(v)[idx] for k, v in init.items()}
+    # FP64 oracle and its conditioning on the sample
+    P, _, _ = oracle.basis(q, pb["nv"], pb["tf"])
+
+    def run_orc(ini):
+        o = oracle.Oracle(pb)
+        st = oracle.state_from(pb, ini)
+        o.solve(st, K)
+        return st["cx"] @ P.T, st["cy"] @ P.T, st["cpsi"] @ P.T
+
+    ox, oy, op = run_orc(sub)
+    rng = np.random.default_rng(0)
+    pert = dict(sub, cx=sub["cx"] * (1 + 2.0 ** -24 * rng.choice([-1, 1], sub["cx"].shape)),
+                cy=sub["cy"] * (1 + 2.0 ** -24 * rng.choice([-1, 1], sub["cy"].shape)))
+    px, py, pp = run_orc(pert)
+    spread = np.maximum(np.maximum(np.abs(px - ox).max(1), np.abs(py - oy).max(1)), np.abs(pp - op).max(1))
+    good = spread <= 5e-5
+    out = {"workload": f"c4: batch {B}, {m} circles, {n} moving obstacles, {q} timesteps, {K} iterations",
+           "sample": int(len(idx)), "well_conditioned": int(good.sum())}
+    p = am.DeviceProblem(pb, "f32")
+    stream = torch.cuda.current_stream()
+    for name, flags, plain in (("fused_fp32", 0, False), ("plain_fp32", 0, True),
+                               ("plain_bf16x3", am.PLAIN_BF16X3, True)):
+        h = am.Handle.for_problem(dict(pb, flags=flags), "f32")
+        states = [am.DeviceState(init, m, n, q, "f32") for _ in range(steps + 1)]
+        ws = torch.empty(am.plain_workspace_size(h, B), dtype=torch.uint8, device="cuda") if plain else None
+        run = (lambda s_: am.solve_plain(h, p, s_, K, ws)) if plain else (lambda s_: am.solve(h, p, s_, K))
+        run(states[0])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for s_ in states[1:]:
+            run(s_)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / steps
+        res = states[-1].numpy()
+        gx, gy, gp = res["cx"][idx] @ P.T, res["cy"][idx] @ P.T, res["cpsi"][idx] @ P.T
+        epos = np.maximum(np.abs(gx - ox).max(1), np.abs(gy - oy).max(1))
+        epsi = np.abs(gp - op).max(1)
+        out[name] = {"ms_per_solve": sec * 1e3, "traj_iter_per_s": B * K / sec,
+                     "max_pos_err_m_well_conditioned": float(epos[good].max()) if good.any() else None,
+                     "max_psi_err_rad_well_conditioned": float(epsi[good].max()) if good.any() else None,
+                     "max_pos_err_m_all": float(epos.max()), "max_psi_err_rad_all": float(epsi.max())}
+        del ws
+    return out
 
 
 def cpu_baseline(pb, init, K, seconds: float):
@@ -189,9 +385,25 @@ def cpu_baseline(pb, init, K, seconds: float):
     t0 = time.perf_counter()
     orc.solve(st, K, nthreads=threads)
     dt = time.perf_counter() - t0
-    return {"value": sample * K / dt, "unit": "traj-AM-iter/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {sample} of {B} trajectories of the same workload, {K} iterations each, "
-                      f"FP64, OpenMP over trajectories ({dt:.1f} s)"}
+    rec = {"value": sample * K / dt, "unit": "traj-AM-iter/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {sample} of {B} trajectories of the same workload, {K} iterations each, "
+                     f"FP64, OpenMP over trajectories ({dt:.1f} s)"}
+    return rec, st
+
+
+def error_vs_oracle(pb, gpu: dict, orc_state: dict):
+    """Max |dx|, |dy| [m] and |dpsi| [rad] of the GPU's final trajectories
+    against the FP64 oracle's on the oracle's sample (same inputs)."""
+    import oracle
+    P, _, _ = oracle.basis(int(pb["q"]), int(pb["nv"]), float(pb["tf"]))
+    S = orc_state["cx"].shape[0]
+    ex = np.abs(gpu["cx"][:S] @ P.T - orc_state["cx"] @ P.T).max(1)
+    ey = np.abs(gpu["cy"][:S] @ P.T - orc_state["cy"] @ P.T).max(1)
+    ep = np.abs(gpu["cpsi"][:S] @ P.T - orc_state["cpsi"] @ P.T).max(1)
+    e = np.maximum(np.maximum(ex, ey), ep)
+    return {"trajectories": int(S), "max_pos_err_m": float(max(ex.max(), ey.max())),
+            "max_psi_err_rad": float(ep.max()), "median_err": float(np.median(e)),
+            "within_1e-3": int((e <= 1e-3).sum())}
 
 
 def main():
@@ -204,6 +416,13 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve", action="store_true",
+                    help="run only the replanning (serving) workload at 50/100/200 Hz and print its JSON")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--uneven", action="store_true", help="run only the 64-problem uneven workload (c3)")
+    ap.add_argument("--precision", action="store_true",
+                    help="run only the precision workload (c4): FP32 vs BF16-split contraction, errors vs oracle")
+    ap.add_argument("--no-serve", action="store_true", help="skip the short serving measurement")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run only a 512 MiB elementwise copy (y = x * 1), the size reference for "
                          "hardware byte counters, and exit")
@@ -223,9 +442,25 @@ def main():
         print(json.dumps({"copy_ref_bytes_read": x.numel() * 4, "copy_ref_bytes_written": y.numel() * 4,
                           "launches": 3}))
         return
+    if args.uneven:
+        print(json.dumps(run_uneven()), flush=True)
+        return
+    if args.precision:
+        print(json.dumps(run_precision()), flush=True)
+        return
+    if args.serve:
+        print(json.dumps(run_serving((50.0, 100.0, 200.0), args.serve_requests, saturation=256)), flush=True)
+        return
     out, pb, init, K = run_gpu(args)
+    if not args.no_serve:
+        sv = run_serving((200.0,), 300, saturation=64)
+        out["serving"] = sv
+        cont = sv["modes"]["continuous"][0]
+        out["p99_replan_latency_ms"] = cont["p99_ms"]
+    final = out.pop("_final")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pb, init, K, args.cpu_seconds)
+        out["cpu_baseline"], orc_state = cpu_baseline(pb, init, K, args.cpu_seconds)
+        out["error_vs_oracle"] = error_vs_oracle(pb, final, orc_state)
     print(json.dumps(out), flush=True)
 
 

@@ -66,13 +66,18 @@ extern "C" {
  *                   (update_lambda_psi); default: the sign of eq.
  *                   (update_lambda_1).
  * AM_Q_CS_ZERO      acceleration cost on the x, y blocks of xi1 only; default:
- *                   on all four blocks (Sec. III-C, "block-diagonal stacking"). */
+ *                   on all four blocks (Sec. III-C, "block-diagonal stacking").
+ * Precision option (not a reading; AM_F32 handles only):
+ * AM_PLAIN_BF16X3   the plain path forms its stacked contraction F^T(F xi - g)
+ *                   with BF16 matrix-core products, FP32 accumulation and a
+ *                   split correction (a_hi b_hi + a_hi b_lo + a_lo b_hi). */
 #define AM_ALPHA_LITERAL  1u
 #define AM_XTILDE_SLACK   2u
 #define AM_PSI_NO_UNWRAP  4u
 #define AM_LAMPSI_LITERAL 8u
 #define AM_Q_CS_ZERO      16u
-#define AM_FLAGS_ALL      31u
+#define AM_PLAIN_BF16X3   32u
+#define AM_FLAGS_ALL      63u
 
 /* per-trajectory residual statistics written by am_residuals */
 #define AM_NRES 12
@@ -184,12 +189,116 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
                    const int32_t *batch, const int32_t *iters, const am_state *states,
                    void *workspace, size_t workspace_bytes, void *stream);
 
+/* Launch shape of the one-launch solve: trajectories per 2*64*tile-thread
+ * block (two wavefronts per trajectory), tile in {1, 2, 4}; default 2.  A
+ * multi-problem launch uses the tile of handles[0]. */
+int am_set_tile(am_handle *h, int32_t tile);
+int am_get_tile(const am_handle *h, int32_t *tile);
+
+/* Autotuner: times am_solve_batch (one warm-up and three timed launches per
+ * candidate, HIP events on `stream`) for every tile on the caller's scratch
+ * state -- which it overwrites -- stores the fastest tile in the handle and
+ * returns it in *best_tile; times_ms (may be NULL) receives the three mean
+ * times in the order 1, 2, 4.  Synchronous. */
+int am_autotune(am_handle *h, const am_problem *p, int32_t batch, int32_t iters, const am_state *scratch,
+                void *stream, int32_t *best_tile, float *times_ms);
+/* The same for a multi-problem launch; the chosen tile is stored in every
+ * handle of the list. */
+int am_autotune_multi(int32_t nprob, am_handle *const *handles, const am_problem *problems,
+                      const int32_t *batch, const int32_t *iters, const am_state *scratch,
+                      void *workspace, size_t workspace_bytes, void *stream, int32_t *best_tile,
+                      float *times_ms);
+
 /* Residual statistics of the current state (AM_RES_* columns), written to
  * device out[batch][AM_NRES] in the handle's dtype.  alpha and d are the
  * closed-form projection of the current trajectories (what the last
  * iteration left).  Reads cx, cc, cy, cs, cpsi, lam, lam_psi of st. */
 int am_residuals(am_handle *h, const am_problem *p, int32_t batch, const am_state *st,
                  void *out, void *stream);
+
+/* Best trajectory of a batch (Fig. 1: the batch returns many locally optimal
+ * trajectories and the one of least cost is used), from the rows that
+ * am_residuals wrote to device `residuals` [batch][AM_NRES] (handle's dtype):
+ * among trajectories with no non-finite value and max |f_c| <= fc_tol
+ * (metres), the least AM_RES_COST; if none qualifies, the least max |f_c|;
+ * ties go to the lower index.  Writes the index (-1 if every trajectory is
+ * non-finite) to device int32 *best and, when values is not NULL, (cost,
+ * max |f_c|) of that trajectory to device values[2] (handle's dtype).
+ * Stream-ordered, asynchronous. */
+int am_select_best(const am_handle *h, int32_t batch, const void *residuals, double fc_tol, int32_t *best,
+                   void *values, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Replanning server: continuous batching of independent solve requests, as a
+ * model-predictive controller issues them (Sec. IV: the batch optimizer runs
+ * inside an MPC loop with the multipliers warm-started from the previous
+ * control loop; Fig. 1 picks the best-cost trajectory of the batch).
+ *
+ * Requests arrive at any time from any thread.  A scheduler thread admits
+ * pending requests, in arrival order, whenever a launch slot is free and the
+ * device-memory budget holds their state and problem table; all requests
+ * admitted together run in one multi-problem launch, and up to `streams`
+ * launches are in flight at once, so new requests start while earlier ones
+ * are still on the GPU.  A request starts from its own initial coefficients
+ * (fresh samples) and, when client c's previous result is still in device
+ * memory with the same batch size, from that result's multipliers (else
+ * from zero multipliers); a client's requests run one after another.  Idle
+ * clients' kept results are dropped least recently used first when the
+ * budget is short.  Latency = completion seen by the scheduler - submission.
+ * ------------------------------------------------------------------------- */
+typedef struct am_server am_server;
+
+#define AM_SERVE_CONTINUOUS 0  /* batch all admissible pending requests per launch   */
+#define AM_SERVE_SEQUENTIAL 1  /* one request per launch, one launch at a time       */
+#define AM_SERVE_PLAIN      2  /* as SEQUENTIAL, with the plain per-sub-step path    */
+
+typedef struct {
+  size_t hbm_budget;            /* device bytes for request state and tables (> 0)      */
+  int32_t streams;              /* launches in flight, 1..16 (forced to 1 unless
+                                   AM_SERVE_CONTINUOUS)                                 */
+  int32_t max_per_launch;       /* requests per launch, 1..256                          */
+  int32_t mode;                 /* AM_SERVE_*                                           */
+  int32_t dtype;                /* AM_F32 or AM_F64; every request's handle must match  */
+  int32_t select_best;          /* 1: after each solve, residuals of every trajectory
+                                   and the best one (am_select_best rule), read back
+                                   with am_server_best; 0: off                          */
+  double fc_tol;                /* collision tolerance of that rule [m], >= 0          */
+} am_server_config;
+
+/* One solve request.  Host arrays are copied during am_server_submit. */
+typedef struct {
+  am_handle *handle;            /* shape of this request (q, nv, m, n, rho, flags)      */
+  int32_t client;               /* warm-start key, >= 0                                 */
+  int32_t batch;                /* trajectories, >= 1                                   */
+  int32_t iters;                /* AM iterations, >= 0                                  */
+  const double *obs_x, *obs_y;  /* host [n][q] obstacle centres                         */
+  const double *obs_a, *obs_b;  /* host [n] semi-axes, un-inflated                      */
+  double r_circle, bc_x[6], bc_y[6], bc_psi[6], v_max, a_max;
+  const double *init;           /* host [batch][5][nv] initial coefficients (cx, cc,
+                                   cy, cs, cpsi), required                              */
+} am_request;
+
+int am_server_create(const am_server_config *cfg, am_server **out);
+/* Queues a request; returns its ticket (>= 0).  Thread-safe, non-blocking.
+ * AM_ERR_INVALID if the request can never fit the budget or is malformed. */
+int am_server_submit(am_server *s, const am_request *r, int64_t *ticket);
+/* Waits up to timeout_s (< 0: forever) for the ticket.  *done = 1 when
+ * finished; then latency_s (may be NULL) receives completion - submission
+ * and, when traj is not NULL, host traj [batch][3][q] (x, y, psi; in the
+ * server's dtype) receives the final trajectories. */
+int am_server_wait(am_server *s, int64_t ticket, double timeout_s, int32_t *done, double *latency_s,
+                   void *traj);
+/* Best trajectory of a finished request (server created with select_best):
+ * its index in the request's batch (-1 if every trajectory is non-finite),
+ * its cost and its max |f_c| (either may be NULL).  AM_ERR_INVALID if the
+ * request has not finished. */
+int am_server_best(am_server *s, int64_t ticket, int32_t *index, double *cost, double *fc_max);
+/* Counters: requests completed, launches issued, peak bytes of the budget
+ * in use, requests that waited for memory (any may be NULL). */
+int am_server_stats(am_server *s, int64_t *completed, int64_t *launches, size_t *peak_bytes,
+                    int64_t *memory_waits);
+/* Finishes in-flight work, stops the scheduler, frees device memory. */
+void am_server_destroy(am_server *s);
 
 /* FP64 copies of the setup results (host buffers, any may be NULL):
  * kkt1_inv [(2nv+6)^2] and kkt2_inv [(nv+6)^2] are the inverses of the KKT

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libam_hip.so")
 AM_OK, AM_ERR_INVALID, AM_ERR_HIP, AM_ERR_SINGULAR, AM_ERR_NONFINITE, AM_ERR_NOMEM = 0, -1, -2, -4, -5, -6
 AM_F32, AM_F64 = 0, 1
 ALPHA_LITERAL, XTILDE_SLACK, PSI_NO_UNWRAP, LAMPSI_LITERAL, Q_CS_ZERO = 1, 2, 4, 8, 16
+PLAIN_BF16X3 = 32
 NRES = 12
 RES_NAMES = ("fc_max", "fc_rms", "fv_max", "fa_max", "slack_max", "heading_max",
              "bc_max", "cost", "clear_level", "v_excess", "a_excess", "nonfinite")
@@ -25,7 +26,11 @@ RES_NAMES = ("fc_max", "fc_rms", "fv_max", "fa_max", "slack_max", "heading_max",
 # every function the header declares
 EXPORTS = ("am_setup", "am_destroy", "am_last_error", "am_solve_batch", "am_plain_workspace_size",
            "am_solve_batch_plain", "am_multi_workspace_size", "am_solve_multi", "am_residuals",
-           "am_setup_matrices")
+           "am_setup_matrices", "am_server_create", "am_server_submit", "am_server_wait",
+           "am_server_stats", "am_server_destroy", "am_set_tile", "am_get_tile", "am_autotune",
+           "am_autotune_multi", "am_select_best", "am_server_best")
+TILES = (1, 2, 4)
+SERVE_CONTINUOUS, SERVE_SEQUENTIAL, SERVE_PLAIN = 0, 1, 2
 
 
 class AmError(RuntimeError):
@@ -52,6 +57,21 @@ class State(ct.Structure):
                                            "alpha", "d", "va", "traj")]
 
 
+class ServerConfig(ct.Structure):
+    _fields_ = [("hbm_budget", ct.c_size_t), ("streams", ct.c_int32), ("max_per_launch", ct.c_int32),
+                ("mode", ct.c_int32), ("dtype", ct.c_int32), ("select_best", ct.c_int32),
+                ("fc_tol", ct.c_double)]
+
+
+class Request(ct.Structure):
+    _fields_ = [("handle", ct.c_void_p), ("client", ct.c_int32), ("batch", ct.c_int32), ("iters", ct.c_int32),
+                ("obs_x", ct.POINTER(ct.c_double)), ("obs_y", ct.POINTER(ct.c_double)),
+                ("obs_a", ct.POINTER(ct.c_double)), ("obs_b", ct.POINTER(ct.c_double)),
+                ("r_circle", ct.c_double), ("bc_x", ct.c_double * 6), ("bc_y", ct.c_double * 6),
+                ("bc_psi", ct.c_double * 6), ("v_max", ct.c_double), ("a_max", ct.c_double),
+                ("init", ct.POINTER(ct.c_double))]
+
+
 _lib = None
 
 
@@ -76,6 +96,22 @@ def lib():
         L.am_residuals.argtypes = [vp, ct.POINTER(Problem), i32, ct.POINTER(State), vp, vp]
         L.am_setup_matrices.argtypes = [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                                         ct.POINTER(ct.c_double)]
+        L.am_server_create.argtypes = [ct.POINTER(ServerConfig), ct.POINTER(vp)]
+        L.am_server_submit.argtypes = [vp, ct.POINTER(Request), ct.POINTER(ct.c_int64)]
+        L.am_server_wait.argtypes = [vp, ct.c_int64, ct.c_double, ct.POINTER(i32), ct.POINTER(ct.c_double), vp]
+        L.am_server_stats.argtypes = [vp, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64), ct.POINTER(sz),
+                                      ct.POINTER(ct.c_int64)]
+        L.am_server_destroy.argtypes = [vp]
+        L.am_server_destroy.restype = None
+        L.am_set_tile.argtypes = [vp, i32]
+        L.am_get_tile.argtypes = [vp, ct.POINTER(i32)]
+        L.am_autotune.argtypes = [vp, ct.POINTER(Problem), i32, i32, ct.POINTER(State), vp, ct.POINTER(i32),
+                                  ct.POINTER(ct.c_float)]
+        L.am_autotune_multi.argtypes = [i32, ct.POINTER(vp), ct.POINTER(Problem), ct.POINTER(i32), ct.POINTER(i32),
+                                        ct.POINTER(State), vp, sz, vp, ct.POINTER(i32), ct.POINTER(ct.c_float)]
+        L.am_select_best.argtypes = [vp, i32, vp, ct.c_double, vp, vp, vp]
+        L.am_server_best.argtypes = [vp, ct.c_int64, ct.POINTER(i32), ct.POINTER(ct.c_double),
+                                     ct.POINTER(ct.c_double)]
         _lib = L
     return _lib
 
@@ -143,6 +179,16 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+    @property
+    def tile(self) -> int:
+        v = ct.c_int32()
+        check(lib().am_get_tile(self._h, ct.byref(v)))
+        return v.value
+
+    @tile.setter
+    def tile(self, t: int):
+        check(lib().am_set_tile(self._h, int(t)))
 
     def matrices(self):
         """(KKT1^-1, KKT2^-1, basis[3, q, nv]) in Bernstein coordinates, FP64."""
@@ -246,9 +292,119 @@ def solve_multi(handles, problems, states, iters, workspace, stream=None):
                                _stream_ptr(stream)))
 
 
+def autotune(h: Handle, p: DeviceProblem, scratch: DeviceState, iters: int, stream=None):
+    """Picks the fastest tile for this batch (overwrites scratch); returns
+    (best tile, {tile: ms})."""
+    best = ct.c_int32()
+    times = (ct.c_float * len(TILES))()
+    check(lib().am_autotune(h.ptr, ct.byref(p.c), scratch.B, int(iters), ct.byref(scratch.c), _stream_ptr(stream),
+                            ct.byref(best), times))
+    return best.value, dict(zip(TILES, list(times)))
+
+
+def autotune_multi(handles, problems, scratch_states, iters, workspace, stream=None):
+    k = len(handles)
+    H = (ct.c_void_p * k)(*[h.ptr.value for h in handles])
+    P = (Problem * k)(*[p.c for p in problems])
+    Bs = (ct.c_int32 * k)(*[s.B for s in scratch_states])
+    Ks = (ct.c_int32 * k)(*([int(iters)] * k))
+    S = (State * k)(*[s.c for s in scratch_states])
+    best = ct.c_int32()
+    times = (ct.c_float * len(TILES))()
+    check(lib().am_autotune_multi(k, H, P, Bs, Ks, S, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                  _stream_ptr(stream), ct.byref(best), times))
+    return best.value, dict(zip(TILES, list(times)))
+
+
 def residuals(h: Handle, p: DeviceProblem, st: DeviceState, out=None, stream=None):
     torch = _torch()
     if out is None:
         out = torch.empty((st.B, NRES), dtype=_dt(h.dtype), device=st.t["cx"].device)
     check(lib().am_residuals(h.ptr, ct.byref(p.c), st.B, ct.byref(st.c), _ptr(out), _stream_ptr(stream)))
     return out
+
+
+def select_best(h: Handle, res, fc_tol: float, stream=None):
+    """am_select_best on residual rows `res` [B, NRES] (device tensor):
+    returns (index, cost, max |f_c|) of the best trajectory (synchronises)."""
+    torch = _torch()
+    idx = torch.full((1,), -2, dtype=torch.int32, device=res.device)
+    vals = torch.zeros((2,), dtype=res.dtype, device=res.device)
+    check(lib().am_select_best(h.ptr, int(res.shape[0]), _ptr(res), float(fc_tol), _ptr(idx), _ptr(vals),
+                               _stream_ptr(stream)))
+    v = vals.cpu().numpy()
+    return int(idx.item()), float(v[0]), float(v[1])
+
+
+class Server:
+    """Continuous-batching replanning server (am_server_*)."""
+
+    def __init__(self, hbm_budget: int, streams: int = 4, max_per_launch: int = 64,
+                 mode: int = SERVE_CONTINUOUS, dtype: str = "f32", select_best: bool = False,
+                 fc_tol: float = 0.05):
+        c = ServerConfig()
+        c.hbm_budget, c.streams, c.max_per_launch = int(hbm_budget), int(streams), int(max_per_launch)
+        c.mode, c.dtype = int(mode), AM_F64 if dtype == "f64" else AM_F32
+        c.select_best, c.fc_tol = int(bool(select_best)), float(fc_tol)
+        self.dtype = dtype
+        s = ct.c_void_p()
+        check(lib().am_server_create(ct.byref(c), ct.byref(s)))
+        self._s = s
+        self._meta = {}
+
+    def submit(self, h: Handle, pb: dict, client: int, batch: int, iters: int, init=None) -> int:
+        r = Request()
+        r.handle, r.client, r.batch, r.iters = h.ptr, int(client), int(batch), int(iters)
+        dp = ct.POINTER(ct.c_double)
+        keep = [np.ascontiguousarray(np.asarray(pb[k], np.float64)) for k in ("ox", "oy", "oa", "ob")]
+        r.obs_x, r.obs_y, r.obs_a, r.obs_b = (a.ctypes.data_as(dp) for a in keep)
+        r.r_circle = float(pb["rc"])
+        r.bc_x[:] = [float(v) for v in pb["bx"]]
+        r.bc_y[:] = [float(v) for v in pb["by"]]
+        r.bc_psi[:] = [float(v) for v in pb["bpsi"]]
+        r.v_max, r.a_max = float(pb["vmax"]), float(pb["amax"])
+        ini = None
+        if init is not None:
+            nv = h.nv
+            z = np.zeros((batch, nv))
+            ini = np.ascontiguousarray(np.stack([np.asarray(init.get(k, z), np.float64)
+                                                 for k in ("cx", "cc", "cy", "cs", "cpsi")], 1))
+            r.init = ini.ctypes.data_as(dp)
+        t = ct.c_int64()
+        check(lib().am_server_submit(self._s, ct.byref(r), ct.byref(t)))
+        self._meta[t.value] = (batch, h.q)
+        return t.value
+
+    def wait(self, ticket: int, timeout: float = -1.0, traj: bool = False):
+        """(done, latency_s, traj [B, 3, q] or None)."""
+        done, lat = ct.c_int32(), ct.c_double()
+        out = None
+        if traj:
+            B, q = self._meta[ticket]
+            out = np.zeros((B, 3, q), dtype=np.float64 if self.dtype == "f64" else np.float32)
+        check(lib().am_server_wait(self._s, int(ticket), float(timeout), ct.byref(done), ct.byref(lat),
+                                   out.ctypes.data_as(ct.c_void_p) if out is not None else None))
+        return bool(done.value), lat.value, out
+
+    def best(self, ticket: int):
+        """(index, cost, max |f_c|) of the best trajectory of a finished request."""
+        i, c, f = ct.c_int32(), ct.c_double(), ct.c_double()
+        check(lib().am_server_best(self._s, int(ticket), ct.byref(i), ct.byref(c), ct.byref(f)))
+        return i.value, c.value, f.value
+
+    def stats(self):
+        c, l, m = ct.c_int64(), ct.c_int64(), ct.c_int64()
+        p = ct.c_size_t()
+        check(lib().am_server_stats(self._s, ct.byref(c), ct.byref(l), ct.byref(p), ct.byref(m)))
+        return dict(completed=c.value, launches=l.value, peak_bytes=p.value, memory_waits=m.value)
+
+    def close(self):
+        if getattr(self, "_s", None) and self._s.value:
+            lib().am_server_destroy(self._s)
+            self._s = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -21,6 +21,7 @@ struct am_handle {
   double r[AM_MAX_CIRCLES];
   int device;
   bool f64;
+  int tile = amk::kDefaultTile;   // trajectories per block of the fused kernel
   double *buf64;       // all FP64 constants
   void *bufT;          // typed copies
   Consts c;
@@ -79,7 +80,7 @@ int check_device(const am_handle *h) {
 }
 
 Desc make_desc(const am_handle *h, const am_problem *p, int32_t batch, int32_t iters,
-               const am_state *st) {
+               const am_state *st, int tile) {
   Desc d;
   std::memset(&d, 0, sizeof d);
   const Consts &c = h->c;
@@ -98,7 +99,7 @@ Desc make_desc(const am_handle *h, const am_problem *p, int32_t batch, int32_t i
   d.q = h->shape.q; d.nv = h->shape.nv; d.m = h->shape.m; d.n = h->shape.n_obs;
   d.B = batch; d.K = iters; d.flags = int(h->shape.flags);
   d.blk0 = 0;
-  d.nblk = (batch + amk::kTrajPerBlock - 1) / amk::kTrajPerBlock;
+  d.nblk = (batch + tile - 1) / tile;
   return d;
 }
 
@@ -111,7 +112,37 @@ size_t lds_limit() {
 
 }  // namespace
 
+namespace {
+
+// Times `reps` launches of fn on the stream with HIP events (after one
+// warm-up launch); returns milliseconds per launch or a negative status.
+template <class F>
+int time_launches(hipStream_t s, int reps, F fn, float *ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = fn();
+  if (rc != AM_OK) return rc;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(AM_ERR_HIP, "hipEventCreate failed");
+  }
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps && rc == AM_OK; ++r) rc = fn();
+  (void)hipEventRecord(e1, s);
+  hipError_t e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != AM_OK) return rc;
+  if (e != hipSuccess) return hip_fail(e, "timing events");
+  *ms = t / float(reps);
+  return AM_OK;
+}
+
+}  // namespace
+
 namespace amk {
+int set_last_error(int code, const char *msg) { return fail(code, "%s", msg); }
 int handle_q(const am_handle *h) { return h->shape.q; }
 int handle_nv(const am_handle *h) { return h->shape.nv; }
 int handle_n(const am_handle *h) { return h->shape.n_obs; }
@@ -139,6 +170,8 @@ int am_setup(const am_shape *s, am_handle **out) {
   if (!(s->rho_psi >= 0.0) || !is_fin(s->rho_psi)) return fail(AM_ERR_INVALID, "rho_psi must be finite and >= 0");
   if (s->dtype != AM_F32 && s->dtype != AM_F64) return fail(AM_ERR_INVALID, "dtype must be AM_F32 or AM_F64");
   if (s->flags & ~AM_FLAGS_ALL) return fail(AM_ERR_INVALID, "unknown flag bits 0x%x", s->flags & ~AM_FLAGS_ALL);
+  if ((s->flags & AM_PLAIN_BF16X3) && s->dtype != AM_F32)
+    return fail(AM_ERR_INVALID, "AM_PLAIN_BF16X3 needs an AM_F32 handle");
 
   am_handle *h = new am_handle();
   h->shape = *s;
@@ -229,12 +262,12 @@ int am_solve_batch(am_handle *h, const am_problem *p, int32_t batch, int32_t ite
   if ((rc = check_state(st)) != AM_OK) return rc;
   if ((rc = check_device(h)) != AM_OK) return rc;
   if (batch == 0) return AM_OK;
-  const Desc d = make_desc(h, p, batch, iters, st);
-  const size_t lds = amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64);
+  const Desc d = make_desc(h, p, batch, iters, st, h->tile);
+  const size_t lds = amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64, h->tile);
   if (lds > lds_limit())
     return fail(AM_ERR_INVALID, "problem needs %zu bytes of LDS, device allows %zu", lds, lds_limit());
   hipError_t e = amk::launch_fused(d, nullptr, 1, d.nblk, h->f64, h->shape.nv,
-                                   static_cast<hipStream_t>(stream), lds);
+                                   static_cast<hipStream_t>(stream), lds, h->tile);
   if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
   return AM_OK;
 }
@@ -275,11 +308,11 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
     if ((rc = check_problem(h, &problems[k])) != AM_OK) return rc;
     if ((rc = check_state(&states[k])) != AM_OK) return rc;
     if ((rc = check_device(h)) != AM_OK) return rc;
-    Desc d = make_desc(h, &problems[k], batch[k], iters[k], &states[k]);
+    Desc d = make_desc(h, &problems[k], batch[k], iters[k], &states[k], h0->tile);
     d.blk0 = blocks;
     blocks += d.nblk;
     descs.push_back(d);
-    lds = std::max(lds, amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64));
+    lds = std::max(lds, amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64, h0->tile));
   }
   if (lds > lds_limit())
     return fail(AM_ERR_INVALID, "a problem needs %zu bytes of LDS, device allows %zu", lds, lds_limit());
@@ -288,7 +321,7 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
   Desc *table = static_cast<Desc *>(workspace);
   hipError_t e = amk::launch_desc_copy(descs.data(), nprob, table, s);
   if (e != hipSuccess) return hip_fail(e, "problem table copy");
-  e = amk::launch_fused(descs[0], table, nprob, blocks, h0->f64, h0->shape.nv, s, lds);
+  e = amk::launch_fused(descs[0], table, nprob, blocks, h0->f64, h0->shape.nv, s, lds, h0->tile);
   if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
   return AM_OK;
 }
@@ -301,10 +334,25 @@ int am_residuals(am_handle *h, const am_problem *p, int32_t batch, const am_stat
   if ((rc = check_problem(h, p)) != AM_OK) return rc;
   if ((rc = check_state(st)) != AM_OK) return rc;
   if ((rc = check_device(h)) != AM_OK) return rc;
-  const Desc d = make_desc(h, p, batch, 0, st);
+  const Desc d = make_desc(h, p, batch, 0, st, h->tile);
   hipError_t e = amk::launch_residuals(d, h->c.tP, h->c.tPd, h->c.tPdd, out, h->f64, h->shape.nv,
                                        static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "residual kernel launch");
+  return AM_OK;
+}
+
+int am_select_best(const am_handle *h, int32_t batch, const void *residuals, double fc_tol, int32_t *best,
+                   void *values, void *stream) {
+  if (!h) return fail(AM_ERR_INVALID, "handle is NULL");
+  if (batch < 0) return fail(AM_ERR_INVALID, "batch must be >= 0");
+  if (!best) return fail(AM_ERR_INVALID, "best is NULL");
+  if (!residuals && batch > 0) return fail(AM_ERR_INVALID, "residuals is NULL");
+  if (!(fc_tol >= 0.0)) return fail(AM_ERR_INVALID, "fc_tol must be >= 0, got %g", fc_tol);
+  int rc;
+  if ((rc = check_device(h)) != AM_OK) return rc;
+  hipError_t e = amk::launch_select_best(residuals, batch, fc_tol, best, values, h->f64,
+                                         static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "select kernel launch");
   return AM_OK;
 }
 
@@ -322,6 +370,77 @@ int am_setup_matrices(const am_handle *h, double *kkt1_inv, double *kkt2_inv, do
   if (basis && e == hipSuccess)
     e = hipMemcpy(basis + 2 * q * nv, h->c.Pdd, sizeof(double) * q * nv, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  return AM_OK;
+}
+
+int am_set_tile(am_handle *h, int32_t tile) {
+  if (!h) return fail(AM_ERR_INVALID, "handle is NULL");
+  for (int t : amk::kTiles)
+    if (t == tile) {
+      h->tile = tile;
+      return AM_OK;
+    }
+  return fail(AM_ERR_INVALID, "tile must be 1, 2 or 4, got %d", tile);
+}
+
+int am_get_tile(const am_handle *h, int32_t *tile) {
+  if (!h || !tile) return fail(AM_ERR_INVALID, "handle and tile must be non-NULL");
+  *tile = h->tile;
+  return AM_OK;
+}
+
+
+int am_autotune(am_handle *h, const am_problem *p, int32_t batch, int32_t iters, const am_state *scratch,
+                void *stream, int32_t *best_tile, float *times_ms) {
+  if (!h) return fail(AM_ERR_INVALID, "handle is NULL");
+  const int keep = h->tile;
+  int best = keep;
+  float best_ms = 0.f;
+  int idx = 0;
+  for (int t : amk::kTiles) {
+    h->tile = t;
+    float ms = 0.f;
+    const int rc = time_launches(static_cast<hipStream_t>(stream), 3,
+                                 [&] { return am_solve_batch(h, p, batch, iters, scratch, stream); }, &ms);
+    if (rc != AM_OK) {
+      h->tile = keep;
+      return rc;
+    }
+    if (times_ms) times_ms[idx] = ms;
+    if (idx == 0 || ms < best_ms) { best_ms = ms; best = t; }
+    ++idx;
+  }
+  h->tile = best;
+  if (best_tile) *best_tile = best;
+  return AM_OK;
+}
+
+int am_autotune_multi(int32_t nprob, am_handle *const *handles, const am_problem *problems, const int32_t *batch,
+                      const int32_t *iters, const am_state *scratch, void *workspace, size_t workspace_bytes,
+                      void *stream, int32_t *best_tile, float *times_ms) {
+  if (nprob < 1 || !handles) return fail(AM_ERR_INVALID, "at least one problem is needed");
+  for (int k = 0; k < nprob; ++k)
+    if (!handles[k]) return fail(AM_ERR_INVALID, "handle %d is NULL", k);
+  const int keep = handles[0]->tile;
+  int best = keep;
+  float best_ms = 0.f;
+  int idx = 0;
+  for (int t : amk::kTiles) {
+    handles[0]->tile = t;
+    float ms = 0.f;
+    const int rc = time_launches(static_cast<hipStream_t>(stream), 3, [&] {
+      return am_solve_multi(nprob, handles, problems, batch, iters, scratch, workspace, workspace_bytes, stream);
+    }, &ms);
+    if (rc != AM_OK) {
+      handles[0]->tile = keep;
+      return rc;
+    }
+    if (times_ms) times_ms[idx] = ms;
+    if (idx == 0 || ms < best_ms) { best_ms = ms; best = t; }
+    ++idx;
+  }
+  for (int k = 0; k < nprob; ++k) handles[k]->tile = best;
+  if (best_tile) *best_tile = best;
   return AM_OK;
 }
 
@@ -344,7 +463,7 @@ int am_solve_batch_plain(am_handle *h, const am_problem *p, int32_t batch, int32
   const size_t need = amk::plain_workspace_bytes(batch, h->shape.q, h->shape.nv, h->shape.m, h->shape.n_obs, h->f64);
   if (!workspace || workspace_bytes < need)
     return fail(AM_ERR_INVALID, "workspace of %zu bytes needed", need);
-  const Desc d = make_desc(h, p, batch, iters, st);
+  const Desc d = make_desc(h, p, batch, iters, st, h->tile);
   hipError_t e = amk::launch_plain(d, workspace, workspace_bytes, h->f64, h->shape.nv,
                                    static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "plain path launch");

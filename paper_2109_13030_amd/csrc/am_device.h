@@ -50,15 +50,22 @@ __device__ __forceinline__ void wave_sync() {
 
 __host__ __device__ constexpr int pad4(int v) { return (v + 3) & ~3; }
 
-// Sums exchanged between the two wavefronts of one trajectory.
-enum { XG_PSIH = 0, XG_T1X, XG_T2X, XG_T1Y, XG_T2Y, XG_TPSI, XG_COUNT };
-constexpr int kXchStride = 16;
+// Sums exchanged between the two wavefronts of one trajectory: per half, 64
+// slots for the per-iteration reduction F^T(F xi - g), U^T(psi - psi_hat)
+// and 16 for U^T psi_hat.
+constexpr int kXchBig = 64;
+constexpr int kXchSmall = 16;
+constexpr int kXchHalf = kXchBig + kXchSmall;
+
+// Reduction scratch: up to kRedRows rows of 32 lane-pair sums.
+constexpr int kRedRows = 56;
+constexpr int kRedRowStride = 36;
 
 // LDS carve-up of the fused kernel, in elements of T.
 struct FusedLds {
   int ox, oy, op;          // centred obstacle tables [n][q]; per-obstacle params [n][8]
   int m1, m2, gf;          // [2nv][2nv], [nv][nv], [2nv][2nv]
-  int xch;                 // [traj][half][group][16] exchange area
+  int xch;                 // [traj][half][kXchHalf] exchange area
   int wave0, wave_stride;  // per-wave areas
   int total;
 };
@@ -81,11 +88,11 @@ __host__ __device__ inline WaveLds wave_layout(int nv) {
   w.lampsi = o; o += p;
   w.tpsi = o; o += p;
   w.tmp = o; o += p;
-  w.red = o; o += 16 * kRedStride;
+  w.red = o; o += kRedRows * kRedRowStride;
   return w;
 }
 
-__host__ __device__ inline FusedLds fused_layout(int q, int n, int nv) {
+__host__ __device__ inline FusedLds fused_layout(int q, int n, int nv, int tile) {
   FusedLds L;
   int o = 0;
   L.ox = o; o += pad4(n * q);
@@ -94,10 +101,10 @@ __host__ __device__ inline FusedLds fused_layout(int q, int n, int nv) {
   L.m1 = o; o += pad4(4 * nv * nv);
   L.m2 = o; o += pad4(nv * nv);
   L.gf = o; o += pad4(4 * nv * nv);
-  L.xch = o; o += kTrajPerBlock * 2 * XG_COUNT * kXchStride;
+  L.xch = o; o += tile * 2 * kXchHalf;
   const WaveLds w = wave_layout(nv);
-  L.wave_stride = pad4(w.red + 16 * kRedStride);
-  L.wave0 = o; o += kWavesPerBlock * L.wave_stride;
+  L.wave_stride = pad4(w.red + kRedRows * kRedRowStride);
+  L.wave0 = o; o += 2 * tile * L.wave_stride;
   L.total = o;
   return L;
 }

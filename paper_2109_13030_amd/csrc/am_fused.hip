@@ -38,24 +38,44 @@ namespace amk {
 namespace {
 
 constexpr int kMaxC = AM_MAX_CIRCLES;
+constexpr int with_psi_rows(int nv) { return 5 * nv; }
 
-// Sum over the 64 lanes of G <= 16 per-lane partials.  On return lane k
-// (k < G) holds the sum of partial k (lanes k+16, k+32, k+48 hold it too).
+// Value of the neighbouring lane (lane ^ 1) through a DPP quad permutation.
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double lane_xor1(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp(int(b & 0xffffffffLL), 0xB1, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), 0xB1, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
+}
+
+// Sums over the 64 lanes of G <= kRedRows per-lane partials.  Lane pairs are
+// added with DPP, the 32 pair sums of partial g go to LDS row g (even lanes
+// write row g, odd lanes row g+1, so every lane stores), and lane g adds its
+// row.  On return lane g (g < G) holds the total of partial g.
 template <typename T, int G>
-__device__ __forceinline__ T wave_sum_rows(const T (&p)[G], T *red, int lane) {
-  static_assert(G <= 16, "at most 16 rows per call");
+__device__ __forceinline__ T wave_sum_many(const T (&p)[G], T *red, int lane) {
+  static_assert(G <= kRedRows, "too many rows");
+  const int odd = lane & 1, col = lane >> 1;
 #pragma unroll
-  for (int k = 0; k < G; ++k) red[k * kRedStride + lane] = p[k];
-  wave_sync();
-  const int row = lane & 15, quarter = lane >> 4;
-  T s = T(0);
-  if (row < G) {
-    const T *src = red + row * kRedStride + quarter * 16;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) s += src[c];
+  for (int k = 0; k < G; k += 2) {
+    const T a = p[k] + lane_xor1(p[k]);
+    if (k + 1 < G) {
+      const T b = p[k + 1] + lane_xor1(p[k + 1]);
+      red[(k + odd) * kRedRowStride + col] = odd ? b : a;
+    } else if (!odd) {
+      red[k * kRedRowStride + col] = a;
+    }
   }
-  s += __shfl_xor(s, 16);
-  s += __shfl_xor(s, 32);
+  wave_sync();
+  T s = T(0);
+  if (lane < G) {
+    const T *row = red + lane * kRedRowStride;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) s += row[c];
+  }
   wave_sync();
   return s;
 }
@@ -84,9 +104,9 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   T *vz = wb + wl.z, *vrhs = wb + wl.rhs, *vlam = wb + wl.lam, *vtr = wb + wl.tr, *vh = wb + wl.h;
   T *vzpsi = wb + wl.zpsi, *vlampsi = wb + wl.lampsi, *vtpsi = wb + wl.tpsi, *vtmp = wb + wl.tmp;
   T *red = wb + wl.red;
-  // exchange area of this trajectory: [half][group][16]
-  T *xch = lds + L.xch + (wave >> 1) * 2 * XG_COUNT * kXchStride;
-  T *xmine = xch + half * XG_COUNT * kXchStride;
+  // exchange area of this trajectory: [half][kXchHalf]
+  T *xch = lds + L.xch + (wave >> 1) * 2 * kXchHalf;
+  T *xmine = xch + half * kXchHalf;
 
   T rr[kMaxC];
   T s1 = T(0), s2 = T(0), rmax = T(0);
@@ -179,10 +199,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     sps = sn;
   };
 
-  // Both waves' halves of one exchange group, added in a fixed order.
-  auto exchange_sum = [&](int g, int k) -> T {
-    return xch[g * kXchStride + k] + xch[XG_COUNT * kXchStride + g * kXchStride + k];
-  };
+  // Both waves' halves of one exchanged sum, added in a fixed order.
+  auto exchange_sum = [&](int slot) -> T { return xch[slot] + xch[kXchHalf + slot]; };
 
   // ---- xi3/xi4 projection of every (circle, obstacle, t), velocity and
   // acceleration, then F^T (F xi - g) into vtr and U^T(psi - psi_hat) into
@@ -196,6 +214,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       // wave-wide vote: obstacles near enough to some lane's robot
       const T ext = rmax * Num<T>::sqrt_(ux * ux + uy * uy);
       uint64_t near_mask = 0;
+#pragma unroll 4
       for (int j = 0; j < n; ++j) {
         const T dx = x - ox[j * q + tt], dy = y - oy[j * q + tt];
         const T reach = ext + op[j * 8 + OP_AMAX];
@@ -278,36 +297,24 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const T ro1x = k1 * dc - Dx, ro2x = k2 * dc - DRx;
     const T ro1y = k1 * ds - Dy, ro2y = k2 * ds - DRy;
     const T rp = psi_sign * (psi - psih);
-    T p1x[NV], p2x[NV], p1y[NV], p2y[NV], pps[NV];
+    // partials of F^T (F xi - g) (x: rows 0..2nv-1, y: 2nv..4nv-1, as
+    // [V W U] on the position block and U on the slack block) and of
+    // U^T (psi - psi_hat) (rows 4nv..5nv-1)
+    constexpr int G = with_psi_rows(NV);
+    T pr[G];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      p1x[k] = Vb[k] * rvx + Wb[k] * rax + Ub[k] * ro1x;
-      p2x[k] = Ub[k] * ro2x;
-      p1y[k] = Vb[k] * rvy + Wb[k] * ray + Ub[k] * ro1y;
-      p2y[k] = Ub[k] * ro2y;
-      pps[k] = Ub[k] * rp;
+      pr[k] = Vb[k] * rvx + Wb[k] * rax + Ub[k] * ro1x;
+      pr[NV + k] = Ub[k] * ro2x;
+      pr[2 * NV + k] = Vb[k] * rvy + Wb[k] * ray + Ub[k] * ro1y;
+      pr[3 * NV + k] = Ub[k] * ro2y;
+      pr[4 * NV + k] = with_psi ? Ub[k] * rp : T(0);
     }
-    const T r0 = wave_sum_rows<T, NV>(p1x, red, lane);
-    const T r1 = wave_sum_rows<T, NV>(p2x, red, lane);
-    const T r2 = wave_sum_rows<T, NV>(p1y, red, lane);
-    const T r3 = wave_sum_rows<T, NV>(p2y, red, lane);
-    T r4 = T(0);
-    if (with_psi) r4 = wave_sum_rows<T, NV>(pps, red, lane);
-    if (lane < NV) {
-      xmine[XG_T1X * kXchStride + lane] = r0;
-      xmine[XG_T2X * kXchStride + lane] = r1;
-      xmine[XG_T1Y * kXchStride + lane] = r2;
-      xmine[XG_T2Y * kXchStride + lane] = r3;
-      xmine[XG_TPSI * kXchStride + lane] = r4;
-    }
+    const T tot = wave_sum_many<T, G>(pr, red, lane);
+    if (lane < G) xmine[lane] = tot;
     __syncthreads();
-    if (lane < NV) {
-      vtr[lane] = exchange_sum(XG_T1X, lane);
-      vtr[NVP + lane] = exchange_sum(XG_T2X, lane);
-      vtr[2 * NVP + lane] = exchange_sum(XG_T1Y, lane);
-      vtr[3 * NVP + lane] = exchange_sum(XG_T2Y, lane);
-      vtpsi[lane] = exchange_sum(XG_TPSI, lane);
-    }
+    if (lane < 4 * NV) vtr[(lane / NV) * NVP + lane % NV] = exchange_sum(lane);
+    else if (lane < G) vtpsi[lane - 4 * NV] = exchange_sum(lane);
     wave_sync();
   };
 
@@ -358,10 +365,10 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     T pp[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) pp[k] = Ub[k] * psih;
-    const T upsi = wave_sum_rows<T, NV>(pp, red, lane);
-    if (lane < NV) xmine[XG_PSIH * kXchStride + lane] = upsi;
+    const T upsi = wave_sum_many<T, NV>(pp, red, lane);
+    if (lane < NV) xmine[kXchBig + lane] = upsi;
     __syncthreads();
-    if (lane < NV) vtmp[lane] = vlampsi[lane] + rho * exchange_sum(XG_PSIH, lane);
+    if (lane < NV) vtmp[lane] = vlampsi[lane] + rho * exchange_sum(kXchBig + lane);
     wave_sync();
     if (lane < NV) {
       T acc = vh[4 * NVP + lane];
@@ -449,9 +456,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   }
 }
 
-template <typename T, int NV>
-__global__ __launch_bounds__(kWave *kWavesPerBlock) void fused_kernel(Desc single, const Desc *table,
-                                                                      int nprob) {
+template <typename T, int NV, int TILE>
+__global__ __launch_bounds__(kWave * 2 * TILE) void fused_kernel(Desc single, const Desc *table, int nprob) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds = reinterpret_cast<T *>(smem_raw);
   int p = 0;
@@ -466,7 +472,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void fused_kernel(Desc singl
   const Desc &D = table ? table[p] : single;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int q = D.q, n = D.n, B = D.B, blk0 = D.blk0;
-  const FusedLds L = fused_layout(q, n, NV);
+  const FusedLds L = fused_layout(q, n, NV, TILE);
 
   // block-wide: obstacle tables (centred), inflated semi-axes, operators
   const T *gox = static_cast<const T *>(D.ox), *goy = static_cast<const T *>(D.oy);
@@ -494,39 +500,50 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void fused_kernel(Desc singl
   // Both trajectories of the block run the loop (it has block-wide
   // barriers); a slot past the end of the batch computes a copy of the last
   // trajectory and stores nothing.
-  const int lt = (int(blockIdx.x) - blk0) * kTrajPerBlock + (wave >> 1);
+  const int lt = (int(blockIdx.x) - blk0) * TILE + (wave >> 1);
   const bool live = lt < B;
   fused_body<T, NV>(D, live ? lt : B - 1, live, wave & 1, lds, L, lane, wave);
 }
 
-template <typename T, int NV>
+template <typename T, int NV, int TILE>
 hipError_t launch_t(const Desc &single, const Desc *table, int nprob, int nblocks, hipStream_t st,
                     size_t lds_bytes) {
   if (lds_bytes > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_kernel<T, NV>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_kernel<T, NV, TILE>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((fused_kernel<T, NV>), dim3(nblocks), dim3(kWave * kWavesPerBlock), lds_bytes, st,
+  hipLaunchKernelGGL((fused_kernel<T, NV, TILE>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes, st,
                      single, table, nprob);
   return hipGetLastError();
 }
 
+template <typename T, int NV>
+hipError_t launch_tile(const Desc &single, const Desc *table, int nprob, int nblocks, hipStream_t st,
+                       size_t lds_bytes, int tile) {
+  switch (tile) {
+    case 1: return launch_t<T, NV, 1>(single, table, nprob, nblocks, st, lds_bytes);
+    case 2: return launch_t<T, NV, 2>(single, table, nprob, nblocks, st, lds_bytes);
+    case 4: return launch_t<T, NV, 4>(single, table, nprob, nblocks, st, lds_bytes);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
-size_t fused_lds_bytes(int q, int n, int nv, bool f64) {
-  return size_t(fused_layout(q, n, nv).total) * (f64 ? 8 : 4);
+size_t fused_lds_bytes(int q, int n, int nv, bool f64, int tile) {
+  return size_t(fused_layout(q, n, nv, tile).total) * (f64 ? 8 : 4);
 }
 
 hipError_t launch_fused(const Desc &single, const Desc *table, int nprob, int nblocks, bool f64,
-                        int nv, hipStream_t st, size_t lds_bytes) {
+                        int nv, hipStream_t st, size_t lds_bytes, int tile) {
   if (nblocks <= 0) return hipSuccess;
   if (f64) {
-    if (nv == 11) return launch_t<double, 11>(single, table, nprob, nblocks, st, lds_bytes);
-    if (nv == 8) return launch_t<double, 8>(single, table, nprob, nblocks, st, lds_bytes);
+    if (nv == 11) return launch_tile<double, 11>(single, table, nprob, nblocks, st, lds_bytes, tile);
+    if (nv == 8) return launch_tile<double, 8>(single, table, nprob, nblocks, st, lds_bytes, tile);
   } else {
-    if (nv == 11) return launch_t<float, 11>(single, table, nprob, nblocks, st, lds_bytes);
-    if (nv == 8) return launch_t<float, 8>(single, table, nprob, nblocks, st, lds_bytes);
+    if (nv == 11) return launch_tile<float, 11>(single, table, nprob, nblocks, st, lds_bytes, tile);
+    if (nv == 8) return launch_tile<float, 8>(single, table, nprob, nblocks, st, lds_bytes, tile);
   }
   return hipErrorInvalidValue;
 }

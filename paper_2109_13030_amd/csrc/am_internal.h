@@ -10,9 +10,11 @@
 namespace amk {
 
 constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kWavesPerBlock = 4;  // 256-thread blocks
-constexpr int kTrajPerBlock = 2;   // fused kernel: two wavefronts per trajectory
-constexpr int kRedStride = 68;     // LDS row stride of the reduction scratch
+constexpr int kWavesPerBlock = 4;  // 256-thread blocks (residual kernel)
+// Fused kernel: two wavefronts per trajectory, `tile` trajectories per block
+// (a launch shape the autotuner chooses among).
+constexpr int kTiles[] = {1, 2, 4};
+constexpr int kDefaultTile = 2;
 
 // One problem of a launch: handle constants, problem data, state, sizes.
 // Pointers to typed data (float or double) are void*; the kernel template
@@ -58,14 +60,19 @@ struct Consts {
 // Launchers (defined in the .hip files).
 hipError_t launch_setup(const am_shape &s, const double *r_dev, const Consts &c, bool f64,
                         hipStream_t st);
-size_t fused_lds_bytes(int q, int n, int nv, bool f64);
+size_t fused_lds_bytes(int q, int n, int nv, bool f64, int tile);
 hipError_t launch_fused(const Desc &single, const Desc *table, int nprob, int nblocks, bool f64,
-                        int nv, hipStream_t st, size_t lds_bytes);
+                        int nv, hipStream_t st, size_t lds_bytes, int tile);
+hipError_t launch_select_best(const void *res, int B, double tol, int32_t *idx, void *vals, bool f64,
+                              hipStream_t st);
 hipError_t launch_residuals(const Desc &d, const void *P, const void *Pd, const void *Pdd, void *out,
                             bool f64, int nv, hipStream_t st);
 hipError_t launch_desc_copy(const Desc *host_descs, int count, Desc *dev_dst, hipStream_t st);
 hipError_t launch_plain(const Desc &d, void *ws, size_t ws_bytes, bool f64, int nv, hipStream_t st);
 size_t plain_workspace_bytes(int B, int q, int nv, int m, int n, bool f64);
+
+// Records the calling thread's last error message (am_last_error); returns code.
+int set_last_error(int code, const char *msg);
 
 // Shape of a handle (for the server).
 int handle_q(const am_handle *h);

@@ -20,9 +20,11 @@ namespace {
 
 constexpr int kThreads = 256;
 
+inline int blocks_for(size_t work) { return int((work + kThreads - 1) / kThreads); }
+
 // Workspace carve-up (elements of T).
 struct PlainWs {
-  size_t rhs, z, lam, zpsi, lampsi, traj8, psi3, psih, alpha, d, va4, chan, total;
+  size_t rhs, z, lam, zpsi, lampsi, traj8, psi3, psih, alpha, d, va4, chan, tot, total;
 };
 
 __host__ __device__ inline PlainWs plain_layout(int B, int q, int nv, int m, int n) {
@@ -45,20 +47,21 @@ __host__ __device__ inline PlainWs plain_layout(int B, int q, int nv, int m, int
   w.d = take(size_t(B) * m * n * q);
   w.va4 = take(size_t(B) * 4 * q);
   w.chan = take(size_t(B) * 9 * q);
+  w.tot = take(size_t(B) * 5 * nv);
   w.total = o;
   return w;
 }
 
 template <typename T>
 struct Ptrs {
-  T *rhs, *z, *lam, *zpsi, *lampsi, *traj8, *psi3, *psih, *alpha, *d, *va4, *chan;
+  T *rhs, *z, *lam, *zpsi, *lampsi, *traj8, *psi3, *psih, *alpha, *d, *va4, *chan, *tot;
 };
 
 template <typename T>
 Ptrs<T> ptrs_of(void *ws, const PlainWs &w) {
   T *b = static_cast<T *>(ws);
   return Ptrs<T>{b + w.rhs, b + w.z, b + w.lam, b + w.zpsi, b + w.lampsi, b + w.traj8,
-                 b + w.psi3, b + w.psih, b + w.alpha, b + w.d, b + w.va4, b + w.chan};
+                 b + w.psi3, b + w.psih, b + w.alpha, b + w.d, b + w.va4, b + w.chan, b + w.tot};
 }
 
 template <typename T>
@@ -334,6 +337,102 @@ __global__ void k_contract(Desc D, Ptrs<T> w, int update) {
   }
 }
 
+// ---- the same contraction on the matrix cores: BF16 operands split into
+// high and low parts (x = hi + lo, both BF16), three products per step
+// (hi*hi + hi*lo + lo*hi) accumulated in FP32.  One wavefront computes a
+// tile of 16 trajectories x 16 outputs of one group with
+// v_mfma_f32_16x16x16_bf16; lane L supplies A[traj L%16][k 4(L/16)..+3],
+// B[k 4(L/16)..+3][out L%16] and receives D[traj 4(L/16)..+3][out L%16].
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float x) {
+  // round to nearest even (inputs are finite)
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return short(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(short h) {
+  return __builtin_bit_cast(float, uint32_t(uint16_t(h)) << 16);
+}
+__device__ __forceinline__ void split_bf16(const float (&v)[4], bf16x4 &hi, bf16x4 &lo) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const short h = bf16_bits(v[i]);
+    hi[i] = h;
+    lo[i] = bf16_bits(v[i] - bf16_value(h));
+  }
+}
+
+template <int NV>
+__global__ void k_contract_mfma(Desc D, Ptrs<float> w) {
+  static_assert(NV <= 16, "one 16-wide output tile per group");
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int l0 = tile * 16;
+  if (l0 >= D.B) return;
+  const int q = D.q, B = D.B;
+  const int r = lane & 15, kq = lane >> 4;     // A row / B column; k quad
+  const int la = l0 + r;                        // trajectory of this lane's A row
+  const float *U = static_cast<const float *>(D.U), *V = static_cast<const float *>(D.V),
+              *W = static_cast<const float *>(D.W);
+  // groups: (channel, basis) pairs, basis 0 = U, 1 = V, 2 = W
+  const int g_ch[5][3] = {{0, 1, 2}, {3, -1, -1}, {4, 5, 6}, {7, -1, -1}, {8, -1, -1}};
+  const int g_bs[5][3] = {{1, 2, 0}, {0, -1, -1}, {1, 2, 0}, {0, -1, -1}, {0, -1, -1}};
+  const int ksteps = (q + 15) / 16;
+  for (int g = 0; g < 5; ++g) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int e = 0; e < 3; ++e) {
+      const int c = g_ch[g][e];
+      if (c < 0) break;
+      const float *basis = g_bs[g][e] == 0 ? U : (g_bs[g][e] == 1 ? V : W);
+      const float *ch = w.chan + size_t(la < B ? la : 0) * 9 * q + size_t(c) * q;
+      for (int ks = 0; ks < ksteps; ++ks) {
+        const int t0 = ks * 16 + kq * 4;
+        float av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int t = t0 + i;
+          av[i] = (la < B && t < q) ? ch[t] : 0.f;
+          bv[i] = (r < NV && t < q) ? basis[t * NV + r] : 0.f;
+        }
+        bf16x4 ah, al, bh, bl;
+        split_bf16(av, ah, al);
+        split_bf16(bv, bh, bl);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int lt = l0 + kq * 4 + i;
+      if (lt < B && r < NV) w.tot[size_t(lt) * 5 * NV + g * NV + r] = acc[i];
+    }
+  }
+}
+
+// ---- multipliers and the next right-hand side from the contraction totals
+template <typename T, int NV>
+__global__ void k_update(Desc D, Ptrs<T> w, int update) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= D.B * 5 * NV) return;
+  const int l = g / (5 * NV), k = g % (5 * NV);
+  const T trv = w.tot[size_t(l) * 5 * NV + k];
+  if (k < 4 * NV) {
+    const int b = k / NV, kk = k % NV, axis = b >> 1, I = (b & 1) * NV + kk;
+    const T *GF = static_cast<const T *>(D.GF), *z = w.z + size_t(l) * 4 * NV;
+    T lv = w.lam[size_t(l) * 4 * NV + k];
+    if (update) lv -= T(D.rho) * trv;
+    T gz = T(0);
+    for (int J = 0; J < 2 * NV; ++J) gz += GF[I * 2 * NV + J] * z[axis * 2 * NV + J];
+    w.lam[size_t(l) * 4 * NV + k] = lv;
+    w.rhs[size_t(l) * 4 * NV + k] = lv + T(D.rho) * (gz - trv);
+  } else if (update) {
+    w.lampsi[size_t(l) * NV + (k - 4 * NV)] -= T(D.rho_psi) * trv;
+  }
+}
+
 // ---- exit: back to Bernstein coordinates, optional outputs
 template <typename T, int NV>
 __global__ void k_exit(Desc D, Ptrs<T> w) {
@@ -376,7 +475,20 @@ __global__ void k_exit(Desc D, Ptrs<T> w) {
   }
 }
 
-inline int blocks_for(size_t work) { return int((work + kThreads - 1) / kThreads); }
+template <typename T, int NV>
+void contract(const Desc &D, const Ptrs<T> &w, hipStream_t st, int update) {
+  const int wave_blocks = (D.B + 3) / 4;
+  if constexpr (sizeof(T) == 4) {
+    if (D.flags & AM_PLAIN_BF16X3) {
+      const int tiles = (D.B + 15) / 16;
+      hipLaunchKernelGGL((k_contract_mfma<NV>), dim3((tiles + 3) / 4), dim3(kThreads), 0, st, D, w);
+      hipLaunchKernelGGL((k_update<T, NV>), dim3(blocks_for(size_t(D.B) * 5 * NV)), dim3(kThreads), 0, st, D, w,
+                         update);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_contract<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w, update);
+}
 
 template <typename T, int NV>
 hipError_t run(const Desc &D, void *ws, hipStream_t st) {
@@ -391,14 +503,14 @@ hipError_t run(const Desc &D, void *ws, hipStream_t st) {
   hipLaunchKernelGGL((k_eval_psi<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
   hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(nproj)), dim3(kThreads), 0, st, D, w);
   hipLaunchKernelGGL((k_targets<T>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
-  hipLaunchKernelGGL((k_contract<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w, 0);
+  contract<T, NV>(D, w, st, 0);
   for (int it = 0; it < D.K; ++it) {
     hipLaunchKernelGGL((k_xi1<T, NV>), dim3(blocks_for(size_t(B) * 4 * NV)), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_xi2<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(nproj)), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_targets<T>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
-    hipLaunchKernelGGL((k_contract<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w, 1);
+    contract<T, NV>(D, w, st, 1);
   }
   const size_t exit_work = std::max(size_t(B) * 5 * NV, size_t(B) * q);
   hipLaunchKernelGGL((k_exit<T, NV>), dim3(blocks_for(exit_work)), dim3(kThreads), 0, st, D, w);

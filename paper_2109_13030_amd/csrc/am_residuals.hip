@@ -158,6 +158,56 @@ hipError_t res_t(const ResArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Best trajectory of a batch from its residual rows: the least cost
+// (AM_RES_COST) among finite trajectories whose collision residual max |f_c|
+// is at most tol; when none qualifies, the least max |f_c| among finite ones;
+// when none is finite, index -1.  Ties go to the lower index, so the choice
+// is a pure function of the residual values.  One 256-thread block.
+constexpr int kSelThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ bool sel_better(int ca, T va, int ia, int cb, T vb, int ib) {
+  if (ca != cb) return ca < cb;
+  if (va != vb) return va < vb;
+  return ia < ib;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSelThreads) void select_best_kernel(const T *res, int B, T tol, int32_t *out_idx,
+                                                                 T *out_vals) {
+  __shared__ int s_c[kSelThreads], s_i[kSelThreads];
+  __shared__ T s_v[kSelThreads];
+  int bc = 3, bi = -1;   // class 0: qualifies, 1: finite only, 3: none yet
+  T bv = T(0);
+  for (int l = threadIdx.x; l < B; l += kSelThreads) {
+    const T *r = res + size_t(l) * AM_NRES;
+    if (r[AM_RES_NONFINITE] != T(0)) continue;
+    const T fc = r[AM_RES_FC_MAX], cost = r[AM_RES_COST];
+    const int c = fc <= tol ? 0 : 1;
+    const T v = c == 0 ? cost : fc;
+    if (sel_better(c, v, l, bc, bv, bi)) { bc = c; bv = v; bi = l; }
+  }
+  s_c[threadIdx.x] = bc; s_v[threadIdx.x] = bv; s_i[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = kSelThreads / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+      const int o = threadIdx.x + w;
+      if (sel_better(s_c[o], s_v[o], s_i[o], s_c[threadIdx.x], s_v[threadIdx.x], s_i[threadIdx.x])) {
+        s_c[threadIdx.x] = s_c[o]; s_v[threadIdx.x] = s_v[o]; s_i[threadIdx.x] = s_i[o];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int b = s_i[0];
+    out_idx[0] = b;
+    if (out_vals) {
+      out_vals[0] = b >= 0 ? res[size_t(b) * AM_NRES + AM_RES_COST] : T(0);
+      out_vals[1] = b >= 0 ? res[size_t(b) * AM_NRES + AM_RES_FC_MAX] : T(0);
+    }
+  }
+}
+
 // Problem-table fill: descriptors travel as kernel arguments (no host staging
 // buffer, nothing to keep alive after the call, capture-safe).
 constexpr int kDescPerCopy = 6;
@@ -190,6 +240,17 @@ hipError_t launch_residuals(const Desc &d, const void *P, const void *Pd, const 
     if (nv == 8) return res_t<float, 8>(a, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_select_best(const void *res, int B, double tol, int32_t *idx, void *vals, bool f64,
+                              hipStream_t st) {
+  if (f64)
+    hipLaunchKernelGGL(select_best_kernel<double>, dim3(1), dim3(kSelThreads), 0, st,
+                       static_cast<const double *>(res), B, tol, idx, static_cast<double *>(vals));
+  else
+    hipLaunchKernelGGL(select_best_kernel<float>, dim3(1), dim3(kSelThreads), 0, st,
+                       static_cast<const float *>(res), B, float(tol), idx, static_cast<float *>(vals));
+  return hipGetLastError();
 }
 
 hipError_t launch_desc_copy(const Desc *host_descs, int count, Desc *dev_dst, hipStream_t st) {

@@ -192,3 +192,41 @@ def uneven_problems(name: str = "c3", count: int | None = None, seed: int | None
         init = make_initial(pb, B, int(rng.integers(1 << 62)), cfg.sigma)
         out.append((pb, init))
     return out
+
+
+# ---------------------------------------------------------------- replanning workload
+
+def serving_clients(count: int, seed: int | None = None):
+    """Robots of the replanning workload: each has its own scene (5 circles,
+    n ~ U{5..30} moving obstacles) and sample count B ~ U{256..2048}."""
+    cfg = CONFIGS["c5"]
+    s = config_seed("c5") if seed is None else seed
+    out = []
+    for child in np.random.SeedSequence(s).spawn(count):
+        rng = np.random.default_rng(child)
+        B = int(rng.integers(cfg.batch[0], cfg.batch[1] + 1))
+        n = int(rng.integers(cfg.n_obs[0], cfg.n_obs[1] + 1))
+        pb = make_problem(cfg, int(rng.integers(1 << 62)), m=cfg.circles, n=n)
+        init = make_initial(pb, B, int(rng.integers(1 << 62)), cfg.sigma)
+        out.append(dict(problem=pb, init=init, batch=B, n=n))
+    return out
+
+
+def replan_problem(pb: dict, step: int, period: float = 0.04) -> dict:
+    """The scene `step` control periods later: every obstacle advanced along
+    its constant velocity (the horizon slides with the controller)."""
+    q, tf = int(pb["q"]), float(pb["tf"])
+    dt = tf / (q - 1)
+    ox, oy = np.asarray(pb["ox"]), np.asarray(pb["oy"])
+    if ox.shape[0] == 0 or q < 2:
+        return dict(pb)
+    vx = (ox[:, 1] - ox[:, 0]) / dt
+    vy = (oy[:, 1] - oy[:, 0]) / dt
+    shift = step * period
+    return dict(pb, ox=ox + vx[:, None] * shift, oy=oy + vy[:, None] * shift)
+
+
+def poisson_arrivals(rate_hz: float, count: int, seed: int = 0) -> np.ndarray:
+    """Arrival times [s] of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_hz, count))

@@ -243,3 +243,93 @@ def test_plain_f32_c2_sampled_against_oracle():
     B = out["cx"].shape[0]
     idx = np.unique(np.concatenate([[0, B - 1], np.random.default_rng(1).choice(B, 22, replace=False)]))
     _fp32_gate(pb, init, 100, idx, out)
+
+
+def test_multi_problem_launch_in_a_graph_replays_exactly():
+    """The multi-problem launch captured in a HIP graph: every replay, with
+    eager resets and synchronisations between replays, equals the eager
+    launch bit for bit."""
+    import torch
+    from paper_2109_13030_amd import am
+    probs = inputs.uneven_problems("c3", count=4, batch_cap=40)
+    hs = [am.Handle.for_problem(pb, "f32") for pb, _ in probs]
+    dps = [am.DeviceProblem(pb, "f32") for pb, _ in probs]
+    pristine = [am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32") for pb, init in probs]
+    work = [am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32") for pb, init in probs]
+    ws = torch.empty(am.multi_workspace_size(len(probs)), dtype=torch.uint8, device="cuda")
+    am.solve_multi(hs, dps, work, 9, ws)
+    torch.cuda.synchronize()
+    eager = [{k: v.clone() for k, v in s.t.items() if v is not None} for s in work]
+
+    def reset():
+        for s, p in zip(work, pristine):
+            for k in am.DeviceState.KEYS:
+                s.t[k].copy_(p.t[k])
+        torch.cuda.synchronize()
+
+    reset()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        am.solve_multi(hs, dps, work, 9, ws)
+    for _ in range(3):
+        reset()
+        g.replay()
+        torch.cuda.synchronize()
+        for s, e in zip(work, eager):
+            for k, v in e.items():
+                assert torch.equal(s.t[k], v), k
+
+
+# ------------------------------------------------------------- precision option: BF16 split contraction
+
+def test_bf16x3_contraction_matches_fp32_contraction():
+    """One iteration: the matrix-core BF16 split contraction reproduces the
+    FP32 multipliers far below plain BF16 resolution (2^-8): the split keeps
+    ~2^-17 per product, and the sums over t partly cancel."""
+    from paper_2109_13030_amd import am
+    pb, init = inputs.workload("c4", batch=45)
+    a = _run_plain(pb, init, 1, "f32")[2].numpy()
+    b = _run_plain(dict(pb, flags=am.PLAIN_BF16X3), init, 1, "f32")[2].numpy()
+    scale = np.abs(a["lam"]).max()
+    assert scale > 0
+    assert np.abs(a["lam"] - b["lam"]).max() <= 1e-3 * scale
+    assert np.abs(a["lam_psi"] - b["lam_psi"]).max() <= 1e-3 * (np.abs(a["lam_psi"]).max() + 1e-30)
+
+
+def test_bf16x3_plain_c4_sampled_against_oracle():
+    """Precision workload c4 (20 moving obstacles), plain path with the BF16
+    split contraction: FP32 tolerance against the FP64 oracle on sampled
+    trajectories (batch reduced to 512 to keep the test short)."""
+    from paper_2109_13030_amd import am
+    pb, init = inputs.workload("c4", batch=512)
+    _, _, st = _run_plain(dict(pb, flags=am.PLAIN_BF16X3), init, 100, "f32", projections=False)
+    out = st.numpy()
+    idx = np.unique(np.concatenate([[0, 511], np.random.default_rng(3).choice(512, 14, replace=False)]))
+    _fp32_gate(pb, init, 100, idx, out)
+
+
+# ------------------------------------------------------------- launch tiles and the autotuner
+
+def test_tiles_give_identical_results_and_autotune_picks_one():
+    """Every launch tile (trajectories per block) computes the same
+    trajectories bit for bit (ragged last block included); the autotuner
+    picks one of them and leaves it set on the handle."""
+    import torch
+    from paper_2109_13030_amd import am
+    pb, init = inputs.workload("c2", batch=9)
+    h = am.Handle.for_problem(pb, "f32")
+    p = am.DeviceProblem(pb, "f32")
+    outs = {}
+    for t in am.TILES:
+        h.tile = t
+        st = am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32")
+        am.solve(h, p, st, 15)
+        torch.cuda.synchronize()
+        outs[t] = st.numpy()
+    for t in am.TILES[1:]:
+        for k in ("cx", "cy", "cpsi", "lam", "lam_psi", "traj"):
+            np.testing.assert_array_equal(outs[t][k], outs[1][k])
+    scratch = am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32")
+    best, times = am.autotune(h, p, scratch, 15)
+    assert best in am.TILES and h.tile == best
+    assert all(v > 0 for v in times.values())

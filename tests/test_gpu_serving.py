@@ -1,0 +1,205 @@
+"""Replanning server (continuous batching) through the C-ABI (needs an
+MI355X): results are the same alone and in the mix, warm starts continue the
+iteration, admission respects the device-memory budget."""
+import numpy as np
+import pytest
+
+from paper_2109_13030_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def am():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_13030_amd import am as amod
+    amod.lib()
+    return amod
+
+
+def _clients(count, cap=300):
+    cl = inputs.serving_clients(count, seed=77)
+    for c in cl:
+        c["batch"] = min(c["batch"], cap)
+        c["init"] = {k: v[:c["batch"]] for k, v in c["init"].items()}
+    return cl
+
+
+def _handles(am, clients):
+    return [am.Handle.for_problem(c["problem"], "f32") for c in clients]
+
+
+def test_same_result_alone_and_in_the_mix(am):
+    """A request's trajectories are bit-identical whether it runs alone or
+    batched with others that arrive at the same time."""
+    clients = _clients(8)
+    hs = _handles(am, clients)
+    K = 12
+    s1 = am.Server(1 << 28, streams=4, max_per_launch=16)
+    t = s1.submit(hs[3], clients[3]["problem"], 0, clients[3]["batch"], K, clients[3]["init"])
+    done, _, alone = s1.wait(t, 60.0, traj=True)
+    assert done
+    s1.close()
+    s2 = am.Server(1 << 28, streams=4, max_per_launch=16)
+    tickets = [s2.submit(h, c["problem"], i, c["batch"], K, c["init"]) for i, (h, c) in enumerate(zip(hs, clients))]
+    outs = [s2.wait(tk, 60.0, traj=True) for tk in tickets]
+    assert all(o[0] for o in outs)
+    np.testing.assert_array_equal(outs[3][2], alone)
+    st = s2.stats()
+    assert st["completed"] == len(clients)
+    s2.close()
+    # and equal to the direct batch solve
+    import torch
+    c = clients[3]
+    p = am.DeviceProblem(c["problem"], "f32")
+    ds = am.DeviceState(c["init"], 5, c["n"], c["problem"]["q"], "f32")
+    am.solve(hs[3], p, ds, K)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ds.t["traj"].cpu().numpy(), alone)
+
+
+def test_warm_start_reuses_the_multipliers(am):
+    """A client's next request starts from fresh samples and the multipliers of
+    its previous result (the paper's MPC warm start of lambda): equal, bit for
+    bit, to two direct solves chained through lambda."""
+    import torch
+    c = _clients(1)[0]
+    h = _handles(am, [c])[0]
+    pb2 = inputs.replan_problem(c["problem"], 1)
+    init2 = inputs.make_initial(pb2, c["batch"], 99)
+    s = am.Server(1 << 28, streams=2, max_per_launch=4)
+    t1 = s.submit(h, c["problem"], 5, c["batch"], 8, c["init"])
+    assert s.wait(t1, 60.0)[0]
+    t2 = s.submit(h, pb2, 5, c["batch"], 8, init2)
+    done, lat, warm = s.wait(t2, 60.0, traj=True)
+    assert done and lat > 0
+    s.close()
+    p1 = am.DeviceProblem(c["problem"], "f32")
+    d1 = am.DeviceState(c["init"], 5, c["n"], c["problem"]["q"], "f32")
+    am.solve(h, p1, d1, 8)
+    torch.cuda.synchronize()
+    lam = d1.t["lam"].cpu().numpy().astype(np.float64)
+    lamp = d1.t["lam_psi"].cpu().numpy().astype(np.float64)
+    p2 = am.DeviceProblem(pb2, "f32")
+    d2 = am.DeviceState(dict(init2, lam=lam, lam_psi=lamp), 5, c["n"], c["problem"]["q"], "f32")
+    am.solve(h, p2, d2, 8)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(warm, d2.t["traj"].cpu().numpy())
+
+
+def test_budget_admission_and_overlap(am):
+    """With room for only a few requests at a time every request still
+    completes; the budget is never exceeded and requests waited for memory."""
+    clients = _clients(10, cap=256)
+    hs = _handles(am, clients)
+    q, nv = clients[0]["problem"]["q"], 11
+    per = 256 * (10 * nv + 3 * q) * 4 + 2 * 30 * q * 4 + 1024
+    budget = 3 * per
+    s = am.Server(budget, streams=4, max_per_launch=8)
+    tickets = [s.submit(h, c["problem"], i, c["batch"], 10, c["init"]) for i, (h, c) in enumerate(zip(hs, clients))]
+    assert all(s.wait(t, 120.0)[0] for t in tickets)
+    # a second round: warm blocks of idle clients are dropped to make room
+    tickets = [s.submit(h, c["problem"], i, c["batch"], 10, c["init"]) for i, (h, c) in enumerate(zip(hs, clients))]
+    assert all(s.wait(t, 120.0)[0] for t in tickets)
+    st = s.stats()
+    assert st["completed"] == 20
+    assert st["peak_bytes"] <= budget
+    assert st["memory_waits"] > 0
+    s.close()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_sequential_and_plain_modes_agree(am, mode):
+    clients = _clients(3, cap=200)
+    hs = _handles(am, clients)
+    K = 10
+    res = {}
+    for md in (0, mode):
+        s = am.Server(1 << 28, streams=2, max_per_launch=8, mode=md)
+        tks = [s.submit(h, c["problem"], i, c["batch"], K, c["init"]) for i, (h, c) in enumerate(zip(hs, clients))]
+        res[md] = [s.wait(t, 120.0, traj=True)[2] for t in tks]
+        s.close()
+    for a, b in zip(res[0], res[mode]):
+        assert np.abs(a - b).max() < 1e-3
+
+
+def test_oversized_request_rejected(am):
+    c = _clients(1)[0]
+    h = _handles(am, [c])[0]
+    s = am.Server(4096, streams=1, max_per_launch=1)
+    with pytest.raises(am.AmError) as e:
+        s.submit(h, c["problem"], 0, c["batch"], 5, c["init"])
+    assert e.value.code == am.AM_ERR_INVALID
+    s.close()
+
+
+def _best_rule(res, tol):
+    """The selection rule of am_select_best, written out over numpy rows."""
+    fin = res[:, 11] == 0
+    ok = fin & (res[:, 0] <= tol)
+    if ok.any():
+        idx = np.flatnonzero(ok)
+        return int(idx[np.lexsort((idx, res[idx, 7]))[0]])
+    if fin.any():
+        idx = np.flatnonzero(fin)
+        return int(idx[np.lexsort((idx, res[idx, 0]))[0]])
+    return -1
+
+
+def test_select_best_rule_on_planted_rows(am):
+    """am_select_best on hand-made residual rows: least cost among rows under
+    the collision tolerance, ties to the lower index, fallback to the least
+    max |f_c|, -1 when every row is non-finite."""
+    import torch
+    c = _clients(1)[0]
+    h = _handles(am, [c])[0]
+    rng = np.random.default_rng(3)
+    for B, case in ((1, "one"), (37, "ties"), (700, "fallback"), (5000, "random"), (64, "nonfinite")):
+        res = np.zeros((B, am.NRES), np.float32)
+        res[:, 0] = rng.uniform(0.0, 0.2, B).astype(np.float32)
+        res[:, 7] = np.round(rng.uniform(1.0, 5.0, B), 1).astype(np.float32)   # many equal costs
+        if case == "fallback":
+            res[:, 0] += 0.5
+        if case == "nonfinite":
+            res[:, 11] = 1.0
+        if case == "ties":
+            res[:, 0] = 0.01
+            res[:, 7] = 2.0
+            res[5:, 7] = 1.5
+        t = torch.as_tensor(res, device="cuda")
+        idx, cost, fc = am.select_best(h, t, 0.05)
+        want = _best_rule(res, np.float32(0.05))
+        assert idx == want, case
+        if case == "ties":
+            assert idx == 5
+        if want >= 0:
+            assert cost == res[want, 7] and fc == res[want, 0]
+
+
+def test_server_reports_the_best_trajectory(am):
+    """With select_best the server returns, per request, the trajectory that
+    the selection rule picks from the residuals of its own result: the same
+    index as residuals + am_select_best on the direct batch solve."""
+    import torch
+    clients = _clients(4)
+    hs = _handles(am, clients)
+    K = 10
+    s = am.Server(1 << 28, streams=2, max_per_launch=8, select_best=True, fc_tol=0.05)
+    tickets = [s.submit(h, c["problem"], i, c["batch"], K, c["init"]) for i, (h, c) in enumerate(zip(hs, clients))]
+    for tk in tickets:
+        assert s.wait(tk, 60.0)[0]
+    got = [s.best(tk) for tk in tickets]
+    s.close()
+    for (h, c), (idx, cost, fc) in zip(zip(hs, clients), got):
+        p = am.DeviceProblem(c["problem"], "f32")
+        ds = am.DeviceState(c["init"], 5, c["n"], c["problem"]["q"], "f32")
+        am.solve(h, p, ds, K)
+        res = am.residuals(h, p, ds)
+        torch.cuda.synchronize()
+        r = res.cpu().numpy()
+        want = _best_rule(r, np.float32(0.05))
+        assert idx == want
+        assert cost == pytest.approx(float(r[want, 7]), rel=0, abs=0)
+        assert fc == pytest.approx(float(r[want, 0]), rel=0, abs=0)

@@ -72,3 +72,19 @@ def test_null_arguments_rejected(amlib):
     assert L.am_solve_multi(0, None, None, None, None, None, None, 0, None) == amlib.AM_OK
     assert L.am_solve_multi(2, None, None, None, None, None, None, 0, None) == amlib.AM_ERR_INVALID
     L.am_destroy(None)
+
+
+@pytest.mark.parametrize("bad", [dict(hbm_budget=0), dict(streams=0), dict(streams=17), dict(max_per_launch=0),
+                                 dict(max_per_launch=257), dict(mode=3), dict(dtype=2)])
+def test_server_rejects_bad_config(amlib, bad):
+    L = amlib.lib()
+    c = amlib.ServerConfig()
+    c.hbm_budget, c.streams, c.max_per_launch, c.mode, c.dtype = 1 << 26, 2, 8, 0, 0
+    for k, v in bad.items():
+        setattr(c, k, v)
+    s = ct.c_void_p()
+    assert L.am_server_create(ct.byref(c), ct.byref(s)) == amlib.AM_ERR_INVALID
+    assert not s.value
+    assert len(L.am_last_error()) > 0
+    assert L.am_server_submit(None, None, None) == amlib.AM_ERR_INVALID
+    L.am_server_destroy(None)
