@@ -423,6 +423,9 @@ def main():
     ap.add_argument("--precision", action="store_true",
                     help="run only the precision workload (c4): FP32 vs BF16-split contraction, errors vs oracle")
     ap.add_argument("--no-serve", action="store_true", help="skip the short serving measurement")
+    ap.add_argument("--mpc", action="store_true",
+                    help="run only the closed-loop MPC benchmark on synthetic crowds (batch 1, 200, 1000)")
+    ap.add_argument("--mpc-episodes", type=int, default=20)
     ap.add_argument("--copy-ref", action="store_true",
                     help="run only a 512 MiB elementwise copy (y = x * 1), the size reference for "
                          "hardware byte counters, and exit")
@@ -447,6 +450,19 @@ def main():
         return
     if args.precision:
         print(json.dumps(run_precision()), flush=True)
+        return
+    if args.mpc:
+        import torch
+
+        from paper_2109_13030_amd import mpc
+        torch.cuda.set_device(0)
+        res = mpc.benchmark(episodes=args.mpc_episodes,
+                            progress=lambda s: print(s, file=sys.stderr, flush=True))
+        print(json.dumps({"workload": "closed-loop MPC, 30-person synthetic crowds (static, same-direction "
+                                      "flow up to 0.3 m/s, opposite flow up to 1.0 m/s), 1.5x0.5 m robot "
+                                      "tracking a straight line at 1 m/s, 40 ms period, 10 warm-started "
+                                      "iterations, 10 s horizon", "episodes": args.mpc_episodes,
+                          "results": res}), flush=True)
         return
     if args.serve:
         print(json.dumps(run_serving((50.0, 100.0, 200.0), args.serve_requests, saturation=256)), flush=True)

@@ -255,6 +255,15 @@ class DeviceState:
             setattr(s, k, _ptr(self.t.get(k)))
         return s
 
+    def load_coefficients(self, init: dict):
+        """Overwrites the coefficients (cx, cc, cy, cs, cpsi; missing ones = 0)
+        in place and keeps the multipliers (a warm start)."""
+        torch = _torch()
+        for k in ("cx", "cc", "cy", "cs", "cpsi"):
+            v = init.get(k)
+            src = np.zeros((self.B, self.nv)) if v is None else np.asarray(v, np.float64).reshape(self.B, self.nv)
+            self.t[k].copy_(torch.as_tensor(src, dtype=self.t[k].dtype))
+
     def numpy(self) -> dict:
         return {k: (v.detach().cpu().numpy().astype(np.float64) if v is not None else None) for k, v in self.t.items()}
 

@@ -51,8 +51,8 @@ __device__ __forceinline__ void wave_sync() {
 __host__ __device__ constexpr int pad4(int v) { return (v + 3) & ~3; }
 
 // Sums exchanged between the two wavefronts of one trajectory: per half, 64
-// slots for the per-iteration reduction F^T(F xi - g), U^T(psi - psi_hat)
-// and 16 for U^T psi_hat.
+// slots for the per-iteration reduction F^T(F xi - g) and the heading
+// multiplier rows, 16 for the heading right-hand side.
 constexpr int kXchBig = 64;
 constexpr int kXchSmall = 16;
 constexpr int kXchHalf = kXchBig + kXchSmall;
@@ -61,46 +61,53 @@ constexpr int kXchHalf = kXchBig + kXchSmall;
 constexpr int kRedRows = 56;
 constexpr int kRedRowStride = 36;
 
-// LDS carve-up of the fused kernel, in elements of T.
+// Pairs and quads of T with the alignment of one LDS vector access.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T x, y;
+};
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+  T a, b, c, d;
+};
+
+// LDS carve-up of the fused kernel, in elements of T.  Offsets are multiples
+// of 4 elements, so Pair and Quad reads are aligned.
 struct FusedLds {
-  int ox, oy, op;          // centred obstacle tables [n][q]; per-obstacle params [n][8]
-  int m1, m2, gf;          // [2nv][2nv], [nv][nv], [2nv][2nv]
+  int oxy;                 // centred obstacle centres, Pair [n][q]
+  int op;                  // per-obstacle parameters [n][8] (OP_*)
+  int m1, gf;              // [2nv][2nv] operators as Quad [a2/4][2nv]
   int xch;                 // [traj][half][kXchHalf] exchange area
   int wave0, wave_stride;  // per-wave areas
   int total;
 };
 
-// Per-wave vectors, each a multiple of nvp = pad4(nv) elements.
+// Per-wave vectors.  Position-block vectors hold one axis in 2nv contiguous
+// entries (x block then slack block), padded to a2 = pad4(2nv).
 struct WaveLds {
-  int z, rhs, lam, tr, h, zpsi, lampsi, tpsi, tmp, red;
+  int z, rhs, zpsi, aux, red;
 };
 
 __host__ __device__ inline WaveLds wave_layout(int nv) {
-  const int p = pad4(nv);
+  const int p = pad4(nv), a2 = pad4(2 * nv);
   WaveLds w;
   int o = 0;
-  w.z = o; o += 4 * p;       // z of (x, c, y, s)
-  w.rhs = o; o += 4 * p;     // lambda + rho F^T g
-  w.lam = o; o += 4 * p;     // lambda in z coordinates
-  w.tr = o; o += 4 * p;      // F^T (F xi - g)
-  w.h = o; o += 5 * p;       // boundary terms of (x, c), (y, s), psi
-  w.zpsi = o; o += p;
-  w.lampsi = o; o += p;
-  w.tpsi = o; o += p;
-  w.tmp = o; o += p;
+  w.z = o; o += 2 * a2;         // z of (x, c) and (y, s)
+  w.rhs = o; o += 2 * a2;       // lambda + rho F^T g
+  w.zpsi = o; o += p;           // heading coefficients
+  w.aux = o; o += 2 * a2 + p;   // set-up and write-back staging
   w.red = o; o += kRedRows * kRedRowStride;
   return w;
 }
 
 __host__ __device__ inline FusedLds fused_layout(int q, int n, int nv, int tile) {
   FusedLds L;
+  const int a2 = pad4(2 * nv);
   int o = 0;
-  L.ox = o; o += pad4(n * q);
-  L.oy = o; o += pad4(n * q);
+  L.oxy = o; o += pad4(2 * n * q);
   L.op = o; o += 8 * n;
-  L.m1 = o; o += pad4(4 * nv * nv);
-  L.m2 = o; o += pad4(nv * nv);
-  L.gf = o; o += pad4(4 * nv * nv);
+  L.m1 = o; o += a2 * 2 * nv;
+  L.gf = o; o += a2 * 2 * nv;
   L.xch = o; o += tile * 2 * kXchHalf;
   const WaveLds w = wave_layout(nv);
   L.wave_stride = pad4(w.red + kRedRows * kRedRowStride);
@@ -109,7 +116,8 @@ __host__ __device__ inline FusedLds fused_layout(int q, int n, int nv, int tile)
   return L;
 }
 
-// Per-obstacle parameter slots in the op table.
-enum { OP_A = 0, OP_B = 1, OP_A2 = 2, OP_B2 = 3, OP_AB = 4, OP_AMAX = 5 };
+// Per-obstacle parameter slots in the op table (inflated semi-axes a, b):
+// the first four are read as one Quad in the projection loop.
+enum { OP_A2 = 0, OP_B2 = 1, OP_AB = 2, OP_AMAX = 3, OP_A = 4, OP_B = 5 };
 
 }  // namespace amk

@@ -1,9 +1,9 @@
 // am_fused.hip -- the whole batched AM iteration (Sec. III-D) in one launch.
 //
 // Two wavefronts own one trajectory for all K iterations: wave h of the pair
-// holds the time steps t = h*ceil(q/2) + lane.  A 256-thread block carries
-// two trajectories and shares the LDS copy of the problem's obstacle table
-// and KKT operators.  Everything the iteration carries (multipliers,
+// holds the time steps t = h*ceil(q/2) + lane.  A block carries `tile`
+// trajectories and shares the LDS copy of the problem's obstacle table and
+// KKT operators.  Everything the iteration carries (multipliers,
 // coefficients, targets) stays in registers and LDS; global memory is read
 // for the initial state and written for the final one only.  Sums over t
 // are formed per wave, exchanged through LDS and added in a fixed order, so
@@ -27,6 +27,14 @@
 //  * lambda <- lambda - rho F^T (F xi - g) (eq. update_lambda_1) and the next
 //    right-hand side lambda + rho F^T g = lambda + rho (F^T F xi - F^T(F xi - g))
 //    share the single reduction F^T (F xi - g).
+//  * The heading step (eq. compute_convex_surrogate) needs M2 (lambda_psi +
+//    rho U^T psi_hat).  The kernel carries mu = M2 lambda_psi instead of
+//    lambda_psi and reduces with the rows of U~ = U M2^T, so one reduction
+//    gives M2 U^T psi_hat directly; the multiplier update (eq.
+//    update_lambda_psi) becomes mu <- mu - rho_psi U~^T (psi - psi_hat).
+//    lambda_psi itself is linear in the summed residuals, so each lane sums
+//    psi - psi_hat over the iterations and lambda_psi is formed once at the
+//    end.
 //  * Positions are shifted by the midpoint of start and goal on entry and back
 //    on exit (exact: the basis reproduces constants, P 1 = 1, Pdot 1 = 0).
 #include <hip/hip_runtime.h>
@@ -38,7 +46,20 @@ namespace amk {
 namespace {
 
 constexpr int kMaxC = AM_MAX_CIRCLES;
-constexpr int with_psi_rows(int nv) { return 5 * nv; }
+constexpr int kVoteChunk = 8;   // obstacles whose positions are loaded together in the vote
+
+// Wave-uniform copies of descriptor fields: the compiler then keeps them in
+// scalar registers and treats loops over them as uniform.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uni(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
+}
 
 // Value of the neighbouring lane (lane ^ 1) through a DPP quad permutation.
 __device__ __forceinline__ float lane_xor1(float v) {
@@ -54,7 +75,8 @@ __device__ __forceinline__ double lane_xor1(double v) {
 // Sums over the 64 lanes of G <= kRedRows per-lane partials.  Lane pairs are
 // added with DPP, the 32 pair sums of partial g go to LDS row g (even lanes
 // write row g, odd lanes row g+1, so every lane stores), and lane g adds its
-// row.  On return lane g (g < G) holds the total of partial g.
+// row with four interleaved accumulators.  On return lane g (g < G) holds
+// the total of partial g.
 template <typename T, int G>
 __device__ __forceinline__ T wave_sum_many(const T (&p)[G], T *red, int lane) {
   static_assert(G <= kRedRows, "too many rows");
@@ -72,22 +94,48 @@ __device__ __forceinline__ T wave_sum_many(const T (&p)[G], T *red, int lane) {
   wave_sync();
   T s = T(0);
   if (lane < G) {
-    const T *row = red + lane * kRedRowStride;
+    const Quad<T> *row = reinterpret_cast<const Quad<T> *>(red + lane * kRedRowStride);
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
 #pragma unroll
-    for (int c = 0; c < 32; ++c) s += row[c];
+    for (int c = 0; c < 8; ++c) {
+      const Quad<T> v = row[c];
+      s0 += v.a; s1 += v.b; s2 += v.c; s3 += v.d;
+    }
+    s = (s0 + s1) + (s2 + s3);
   }
   wave_sync();
   return s;
 }
 
+// Row I of a [2nv][2nv] operator stored as Quad [a2/4][2nv] times the
+// 2nv-vector v (contiguous, 16-byte aligned, padded to a2).
+template <typename T, int NV>
+__device__ __forceinline__ T row_dot(const T *op, int I, const T *v) {
+  constexpr int N2 = 2 * NV, C = pad4(N2) / 4;
+  const Quad<T> *o = reinterpret_cast<const Quad<T> *>(op);
+  const Quad<T> *vv = reinterpret_cast<const Quad<T> *>(v);
+  T acc0 = T(0), acc1 = T(0);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const Quad<T> a = o[c * N2 + I], b = vv[c];
+    acc0 += a.a * b.a;
+    acc1 += a.b * b.b;
+    if (4 * c + 2 < N2) acc0 += a.c * b.c;
+    if (4 * c + 3 < N2) acc1 += a.d * b.d;
+  }
+  return acc0 + acc1;
+}
+
 template <typename T, int NV>
 __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds, const FusedLds &L,
                            int lane, int wave) {
-  constexpr int NVP = pad4(NV);
+  constexpr int A2 = pad4(2 * NV), N2 = 2 * NV;
+  constexpr int G = 5 * NV;   // rows of the per-iteration reduction
   // descriptor fields used in the loop, as locals
-  const int q = Dsrc.q, m = Dsrc.m, n = Dsrc.n, flags = Dsrc.flags, K = Dsrc.K;
-  const T rho = T(Dsrc.rho), rhop = T(Dsrc.rho_psi), vmax = T(Dsrc.vmax), amax = T(Dsrc.amax);
-  const double offx = Dsrc.offx, offy = Dsrc.offy;
+  const int q = uni(Dsrc.q), m = uni(Dsrc.m), n = uni(Dsrc.n), flags = uni(Dsrc.flags), K = uni(Dsrc.K);
+  const T rho = uni(T(Dsrc.rho)), rhop = uni(T(Dsrc.rho_psi)), vmax = uni(T(Dsrc.vmax)),
+          amax = uni(T(Dsrc.amax));
+  const double offx = uni(Dsrc.offx), offy = uni(Dsrc.offy);
   const bool slack = flags & AM_XTILDE_SLACK;
   const bool literal_alpha = flags & AM_ALPHA_LITERAL;
   const bool unwrap = !(flags & AM_PSI_NO_UNWRAP);
@@ -96,13 +144,18 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   const int t = half * hq + lane;
   const bool tv = lane < hq && t < q;
   const int tt = tv ? t : 0;
+  // lane roles in the wave-uniform steps: row (axis, I) of the position
+  // block for lane < 4 nv, row `lane` of the heading block for lane < nv
+  const bool prow = lane < 2 * N2, hrow = lane < NV;
+  const int axis = prow ? lane / N2 : 0, I = prow ? lane % N2 : 0;
 
-  const T *ox = lds + L.ox, *oy = lds + L.oy, *op = lds + L.op;
-  const T *M1 = lds + L.m1, *M2 = lds + L.m2, *GF = lds + L.gf;
+  const Pair<T> *oxy = reinterpret_cast<const Pair<T> *>(lds + L.oxy);
+  const T *op = lds + L.op;
+  const Quad<T> *opq = reinterpret_cast<const Quad<T> *>(lds + L.op);
+  const T *M1 = lds + L.m1, *GF = lds + L.gf;
   const WaveLds wl = wave_layout(NV);
   T *wb = lds + L.wave0 + wave * L.wave_stride;
-  T *vz = wb + wl.z, *vrhs = wb + wl.rhs, *vlam = wb + wl.lam, *vtr = wb + wl.tr, *vh = wb + wl.h;
-  T *vzpsi = wb + wl.zpsi, *vlampsi = wb + wl.lampsi, *vtpsi = wb + wl.tpsi, *vtmp = wb + wl.tmp;
+  T *vz = wb + wl.z, *vrhs = wb + wl.rhs, *vzpsi = wb + wl.zpsi, *vaux = wb + wl.aux;
   T *red = wb + wl.red;
   // exchange area of this trajectory: [half][kXchHalf]
   T *xch = lds + L.xch + (wave >> 1) * 2 * kXchHalf;
@@ -112,7 +165,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   T s1 = T(0), s2 = T(0), rmax = T(0);
 #pragma unroll
   for (int i = 0; i < kMaxC; ++i) {
-    rr[i] = i < m ? T(Dsrc.r[i]) : T(0);
+    rr[i] = i < m ? uni(T(Dsrc.r[i])) : T(0);
     s1 += rr[i];
     s2 += rr[i] * rr[i];
     rmax = fmax(rmax, fabs(rr[i]));
@@ -120,49 +173,52 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   s1 *= T(n);   // n sum r_i
   s2 *= T(n);   // n sum r_i^2
 
-  // ---- per-lane basis rows (constant for the whole solve)
+  // ---- per-lane basis rows (constant for the whole solve), U~ = U M2^T
   const T *gU = static_cast<const T *>(Dsrc.U), *gV = static_cast<const T *>(Dsrc.V),
-          *gW = static_cast<const T *>(Dsrc.W);
-  T Ub[NV], Vb[NV], Wb[NV];
+          *gW = static_cast<const T *>(Dsrc.W), *gUt = static_cast<const T *>(Dsrc.Ut),
+          *gM2 = static_cast<const T *>(Dsrc.M2);
+  T Ub[NV], Vb[NV], Wb[NV], Ut[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     Ub[k] = tv ? gU[tt * NV + k] : T(0);
     Vb[k] = tv ? gV[tt * NV + k] : T(0);
     Wb[k] = tv ? gW[tt * NV + k] : T(0);
+    Ut[k] = tv ? gUt[tt * NV + k] : T(0);
   }
 
   // ---- boundary terms h = H b (centred positions) and the initial state
   const double *R = Dsrc.R, *Rinv = Dsrc.Rinv;
-  if (lane < 4 * NV) {
-    const int b = lane / NV, kk = lane % NV, axis = b >> 1;
+  T hreg = T(0), lam = T(0), hpsi = T(0), lampsi0 = T(0);
+  if (prow) {
     const double *bb = axis == 0 ? Dsrc.bx : Dsrc.by;
     const double off = axis == 0 ? offx : offy;
     const T *H1 = static_cast<const T *>(Dsrc.H1);
-    const int I = (b & 1) * NV + kk;
     double hsum = 0.0;
     for (int e = 0; e < 6; ++e) {
       const double be = (e == 0 || e == 3) ? bb[e] - off : bb[e];
       hsum += double(H1[I * 6 + e]) * be;
     }
-    vh[b * NVP + kk] = T(hsum);
+    hreg = T(hsum);
     // z = R (c - off): the basis reproduces constants, so shifting all
     // coefficients of a position shifts its curve
+    const int b = axis * 2 + (I >= NV), kk = I % NV;
     const T *src = static_cast<const T *>(b == 0 ? Dsrc.cx : (b == 1 ? Dsrc.cc : (b == 2 ? Dsrc.cy : Dsrc.cs)));
     const double coff = (b == 0) ? offx : ((b == 2) ? offy : 0.0);
     double zz = 0.0;
     for (int j = kk; j < NV; ++j) zz += R[kk * NV + j] * (double(src[size_t(l) * NV + j]) - coff);
-    vz[b * NVP + kk] = T(zz);
+    vz[axis * A2 + I] = T(zz);
     // lambda_z = R^-T lambda
     const T *glam = static_cast<const T *>(Dsrc.lam);
     double lz = 0.0;
     for (int j = 0; j <= kk; ++j) lz += Rinv[j * NV + kk] * double(glam[size_t(l) * 4 * NV + b * NV + j]);
-    vlam[b * NVP + kk] = T(lz);
-  } else if (lane < 5 * NV) {
-    const int kk = lane - 4 * NV;
+    lam = T(lz);
+  }
+  if (hrow) {
+    const int kk = lane;
     const T *H2 = static_cast<const T *>(Dsrc.H2);
     double hsum = 0.0;
     for (int e = 0; e < 6; ++e) hsum += double(H2[kk * 6 + e]) * Dsrc.bpsi[e];
-    vh[4 * NVP + kk] = T(hsum);
+    hpsi = T(hsum);
     const T *src = static_cast<const T *>(Dsrc.cpsi);
     double zz = 0.0;
     for (int j = kk; j < NV; ++j) zz += R[kk * NV + j] * double(src[size_t(l) * NV + j]);
@@ -170,18 +226,27 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const T *glp = static_cast<const T *>(Dsrc.lampsi);
     double lz = 0.0;
     for (int j = 0; j <= kk; ++j) lz += Rinv[j * NV + kk] * double(glp[size_t(l) * NV + j]);
-    vlampsi[kk] = T(lz);
+    lampsi0 = T(lz);
+    vaux[kk] = lampsi0;
+  }
+  wave_sync();
+  // mu = M2 lambda_psi (heading rows)
+  T mu = T(0);
+  if (hrow) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) mu += gM2[lane * NV + j] * vaux[j];
   }
   wave_sync();
 
   // ---- per-lane trajectory values at t
   T x, xd, xdd, cc, y, yd, ydd, ss, psi, cps, sps, psih;
+  T racc = T(0);   // sum over the iterations of psi_sign (psi - psi_hat) at t
 
   auto eval_xy = [&]() {
     T a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      const T zx = vz[k], zc = vz[NVP + k], zy = vz[2 * NVP + k], zs = vz[3 * NVP + k];
+      const T zx = vz[k], zc = vz[NV + k], zy = vz[A2 + k], zs = vz[A2 + NV + k];
       a0 += Ub[k] * zx; a1 += Vb[k] * zx; a2 += Wb[k] * zx; a3 += Ub[k] * zc;
       b0 += Ub[k] * zy; b1 += Vb[k] * zy; b2 += Wb[k] * zy; b3 += Ub[k] * zs;
     }
@@ -202,50 +267,85 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // Both waves' halves of one exchanged sum, added in a fixed order.
   auto exchange_sum = [&](int slot) -> T { return xch[slot] + xch[kXchHalf + slot]; };
 
+  // Projection of one obstacle's rows at this lane's t for every circle
+  // (fast form; a non-finite sum is redone element by element afterwards).
+  // p = (a^2, b^2, ab, max(a, b)) of the inflated ellipse.
+  T Sx[kMaxC], Sy[kMaxC];
+  auto project_obstacle = [&](T ux, T uy, const Pair<T> o, const Quad<T> p) {
+    const T dxj = x - o.x, dyj = y - o.y;
+#pragma unroll
+    for (int i = 0; i < kMaxC; ++i) {
+      if (i < m) {
+        const T xt = dxj + rr[i] * ux, yt = dyj + rr[i] * uy;
+        const T r2 = p.b * xt * xt + p.a * yt * yt;   // b^2 x~^2 + a^2 y~^2
+        const T f1 = fmax(T(0), p.c * Num<T>::rsqrt(r2) - T(1));
+        Sx[i] += xt * f1;
+        Sy[i] += yt * f1;
+      }
+    }
+  };
+
   // ---- xi3/xi4 projection of every (circle, obstacle, t), velocity and
-  // acceleration, then F^T (F xi - g) into vtr and U^T(psi - psi_hat) into
-  // vtpsi (both halves of t summed).
+  // acceleration, then the per-wave partial sums of F^T (F xi - g) (rows
+  // 0..4nv-1) and U~^T (psi - psi_hat) (rows 4nv..5nv-1), exchanged between
+  // the two waves; afterwards lane k < 4nv holds row k of the total in `tr`
+  // and lane k < nv row 4nv+k in `trpsi`.
+  T tr = T(0), trpsi = T(0);
   auto project_reduce = [&](bool with_psi) {
     const T ux = slack ? cc : cps, uy = slack ? ss : sps;
-    T Sx[kMaxC], Sy[kMaxC];
 #pragma unroll
     for (int i = 0; i < kMaxC; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
     if (!literal_alpha) {
-      // wave-wide vote: obstacles near enough to some lane's robot
+      // wave-wide vote: obstacles near enough to some lane's robot.  The
+      // positions of a chunk of obstacles are loaded before any is tested.
       const T ext = rmax * Num<T>::sqrt_(ux * ux + uy * uy);
       uint64_t near_mask = 0;
-#pragma unroll 4
-      for (int j = 0; j < n; ++j) {
-        const T dx = x - ox[j * q + tt], dy = y - oy[j * q + tt];
-        const T reach = ext + op[j * 8 + OP_AMAX];
-        const bool near = tv && (dx * dx + dy * dy < reach * reach);
-        if (__any(near)) near_mask |= uint64_t(1) << j;
-      }
-      while (near_mask) {
-        const int j = __builtin_ctzll(near_mask);
-        near_mask &= near_mask - 1;
-        const T oxj = ox[j * q + tt], oyj = oy[j * q + tt];
-        const T a2 = op[j * 8 + OP_A2], b2 = op[j * 8 + OP_B2], ab = op[j * 8 + OP_AB];
+      for (int j0 = 0; j0 < n; j0 += kVoteChunk) {
+        Pair<T> o[kVoteChunk];
+        T am[kVoteChunk];
 #pragma unroll
-        for (int i = 0; i < kMaxC; ++i) {
-          if (i < m) {
-            const T xt = x + rr[i] * ux - oxj, yt = y + rr[i] * uy - oyj;
-            const T r2 = b2 * xt * xt + a2 * yt * yt;
-            const T f1 = fmax(T(0), ab * Num<T>::rsqrt(r2) - T(1));
-            Sx[i] += xt * f1;
-            Sy[i] += yt * f1;
-          }
+        for (int k = 0; k < kVoteChunk; ++k) {
+          const int j = j0 + k < n ? j0 + k : n - 1;
+          o[k] = oxy[j * q + tt];
+          am[k] = op[j * 8 + OP_AMAX];
+        }
+#pragma unroll
+        for (int k = 0; k < kVoteChunk; ++k) {
+          const T dx = x - o[k].x, dy = y - o[k].y;
+          const T reach = ext + am[k];
+          const bool near = tv & (dx * dx + dy * dy < reach * reach);
+          const uint64_t bal = __ballot(near);
+          if (j0 + k < n && bal != 0) near_mask |= uint64_t(1) << (j0 + k);
+        }
+      }
+      // active obstacles, the next one's data loaded while this one is used
+      if (near_mask) {
+        int j = __builtin_ctzll(near_mask);
+        near_mask &= near_mask - 1;
+        Pair<T> o = oxy[j * q + tt];
+        Quad<T> p = opq[j * 2];
+        while (true) {
+          const bool more = near_mask != 0;
+          const int jn = more ? __builtin_ctzll(near_mask) : j;
+          near_mask &= near_mask - 1;
+          const Pair<T> on = oxy[jn * q + tt];
+          const Quad<T> pn = opq[jn * 2];
+          project_obstacle(ux, uy, o, p);
+          if (!more) break;
+          j = jn;
+          o = on;
+          p = pn;
         }
       }
     } else {
       for (int j = 0; j < n; ++j) {
-        const T oxj = ox[j * q + tt], oyj = oy[j * q + tt];
+        const Pair<T> o = oxy[j * q + tt];
         const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
         const T a2 = op[j * 8 + OP_A2], b2 = op[j * 8 + OP_B2];
 #pragma unroll
         for (int i = 0; i < kMaxC; ++i) {
           if (i < m) {
-            const T xt = x + rr[i] * ux - oxj, yt = y + rr[i] * uy - oyj;
+            const T xt = x + rr[i] * ux - o.x, yt = y + rr[i] * uy - o.y;
             const T xx = xt * xt, yy = yt * yt;
             const T kap = fmax(Num<T>::rsqrt(xx + yy), (a * xx + b * yy) / (a2 * xx + b2 * yy));
             Sx[i] += xt * (a * kap - T(1));
@@ -261,7 +361,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       if (i < m && !(isfinite(Sx[i]) && isfinite(Sy[i]))) {
         T sx = T(0), sy = T(0);
         for (int j = 0; j < n; ++j) {
-          const T xt = x + rr[i] * ux - ox[j * q + tt], yt = y + rr[i] * uy - oy[j * q + tt];
+          const Pair<T> o = oxy[j * q + tt];
+          const T xt = x + rr[i] * ux - o.x, yt = y + rr[i] * uy - o.y;
           const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
           if (xt == T(0) && yt == T(0)) {
             sx += a;   // alpha = 0, d = 1: target (x_j + a, y_j)
@@ -296,11 +397,11 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const T k1 = slack ? T(0) : s1, k2 = (slack ? T(0) : s2) + T(1);
     const T ro1x = k1 * dc - Dx, ro2x = k2 * dc - DRx;
     const T ro1y = k1 * ds - Dy, ro2y = k2 * ds - DRy;
-    const T rp = psi_sign * (psi - psih);
+    const T rp = with_psi ? psi_sign * (psi - psih) : T(0);
+    racc += rp;
     // partials of F^T (F xi - g) (x: rows 0..2nv-1, y: 2nv..4nv-1, as
     // [V W U] on the position block and U on the slack block) and of
-    // U^T (psi - psi_hat) (rows 4nv..5nv-1)
-    constexpr int G = with_psi_rows(NV);
+    // U~^T (psi - psi_hat) (rows 4nv..5nv-1)
     T pr[G];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -308,54 +409,35 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       pr[NV + k] = Ub[k] * ro2x;
       pr[2 * NV + k] = Vb[k] * rvy + Wb[k] * ray + Ub[k] * ro1y;
       pr[3 * NV + k] = Ub[k] * ro2y;
-      pr[4 * NV + k] = with_psi ? Ub[k] * rp : T(0);
+      pr[4 * NV + k] = Ut[k] * rp;
     }
     const T tot = wave_sum_many<T, G>(pr, red, lane);
     if (lane < G) xmine[lane] = tot;
     __syncthreads();
-    if (lane < 4 * NV) vtr[(lane / NV) * NVP + lane % NV] = exchange_sum(lane);
-    else if (lane < G) vtpsi[lane - 4 * NV] = exchange_sum(lane);
-    wave_sync();
-  };
-
-  // lambda + rho (F^T F z - F^T(F xi - g)) for lane k < 4 NV
-  auto next_rhs = [&](int k) {
-    const int b = k / NV, kk = k % NV, axis = b >> 1;
-    const int I = (b & 1) * NV + kk;
-    const T *zax = vz + axis * 2 * NVP;
-    T gz = T(0);
-#pragma unroll
-    for (int J = 0; J < 2 * NV; ++J) gz += GF[I * 2 * NV + J] * zax[(J / NV) * NVP + J % NV];
-    return vlam[b * NVP + kk] + rho * (gz - vtr[b * NVP + kk]);
+    if (prow) tr = exchange_sum(lane);
+    if (hrow) trpsi = exchange_sum(4 * NV + lane);
   };
 
   // ---- step 1 of the AM list: initial xi3, xi4 from the given trajectory
   eval_xy();
   eval_psi();
   psih = psi;
+  T gz = prow ? row_dot<T, NV>(GF, I, vz + axis * A2) : T(0);   // row of F^T F z
   project_reduce(false);
-  if (lane < 4 * NV) {
-    const T v = next_rhs(lane);
-    vrhs[(lane / NV) * NVP + lane % NV] = v;
-  }
+  if (prow) vrhs[axis * A2 + I] = lam + rho * (gz - tr);
   wave_sync();
 
   for (int it = 0; it < K; ++it) {
     // ---- xi1: [z; mu] = KKT^-1 [lambda + rho F^T g; b]  (eqs. over_3, zeta_1_sepration_3)
-    if (lane < 4 * NV) {
-      const int b = lane / NV, kk = lane % NV, axis = b >> 1;
-      const int I = (b & 1) * NV + kk;
-      const T *rax = vrhs + axis * 2 * NVP;
-      T acc = vh[b * NVP + kk];
-#pragma unroll
-      for (int J = 0; J < 2 * NV; ++J) acc += M1[I * 2 * NV + J] * rax[(J / NV) * NVP + J % NV];
-      vz[b * NVP + kk] = acc;
-    }
+    if (prow) vz[axis * A2 + I] = hreg + row_dot<T, NV>(M1, I, vrhs + axis * A2);
     wave_sync();
     eval_xy();
+    // F^T F z of the new z, used by the next right-hand side
+    gz = prow ? row_dot<T, NV>(GF, I, vz + axis * A2) : T(0);
 
     // ---- xi2: psi_hat = atan2(s, c) on the branch nearest psi^k, then the
-    // heading QP (eq. compute_convex_surrogate)
+    // heading QP (eq. compute_convex_surrogate):
+    // z_psi = h + M2 lambda_psi + rho M2 U^T psi_hat = h + mu + rho U~^T psi_hat
     {
       T ph;
       if (unwrap) ph = psi + atan2z(ss * cps - cc * sps, cc * cps + ss * sps);
@@ -364,35 +446,34 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     }
     T pp[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) pp[k] = Ub[k] * psih;
+    for (int k = 0; k < NV; ++k) pp[k] = Ut[k] * psih;
     const T upsi = wave_sum_many<T, NV>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = upsi;
     __syncthreads();
-    if (lane < NV) vtmp[lane] = vlampsi[lane] + rho * exchange_sum(kXchBig + lane);
-    wave_sync();
-    if (lane < NV) {
-      T acc = vh[4 * NVP + lane];
-#pragma unroll
-      for (int j = 0; j < NV; ++j) acc += M2[lane * NV + j] * vtmp[j];
-      vzpsi[lane] = acc;
-    }
+    if (hrow) vzpsi[lane] = hpsi + mu + rho * exchange_sum(kXchBig + lane);
     wave_sync();
     eval_psi();
 
     // ---- xi3, xi4 and the multipliers (eqs. update_lambda_1, update_lambda_psi)
     project_reduce(true);
-    if (lane < 4 * NV) {
-      const int b = lane / NV, kk = lane % NV;
-      vlam[b * NVP + kk] -= rho * vtr[b * NVP + kk];
-    } else if (lane < 5 * NV) {
-      const int kk = lane - 4 * NV;
-      vlampsi[kk] -= rhop * vtpsi[kk];
+    if (prow) {
+      lam -= rho * tr;
+      vrhs[axis * A2 + I] = lam + rho * (gz - tr);
     }
+    if (hrow) mu -= rhop * trpsi;
     wave_sync();
-    if (lane < 4 * NV) {
-      const T v = next_rhs(lane);
-      vrhs[(lane / NV) * NVP + lane % NV] = v;
-    }
+  }
+
+  // ---- lambda_psi = lambda_psi(0) - rho_psi U^T (sum of psi - psi_hat)
+  {
+    T pp[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) pp[k] = Ub[k] * racc;
+    const T s = wave_sum_many<T, NV>(pp, red, lane);
+    if (lane < NV) xmine[kXchBig + lane] = s;
+    __syncthreads();
+    if (hrow) vaux[2 * A2 + lane] = lampsi0 - rhop * exchange_sum(kXchBig + lane);
+    if (prow) vaux[axis * A2 + I] = lam;
     wave_sync();
   }
 
@@ -400,20 +481,22 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 
   // ---- state back to Bernstein coordinates (written by the first half)
   if (half == 0) {
-    if (lane < 4 * NV) {
-      const int b = lane / NV, kk = lane % NV;
+    if (prow) {
+      const int b = axis * 2 + (I >= NV), kk = I % NV;
       T *dst = static_cast<T *>(b == 0 ? Dsrc.cx : (b == 1 ? Dsrc.cc : (b == 2 ? Dsrc.cy : Dsrc.cs)));
       const double coff = (b == 0) ? offx : ((b == 2) ? offy : 0.0);
+      const int base = axis * A2 + (I >= NV ? NV : 0);
       double c = 0.0, lc = 0.0;
-      for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * double(vz[b * NVP + j]);
-      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(vlam[b * NVP + j]);
+      for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * double(vz[base + j]);
+      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(vaux[base + j]);
       dst[size_t(l) * NV + kk] = T(c + coff);
       static_cast<T *>(Dsrc.lam)[size_t(l) * 4 * NV + b * NV + kk] = T(lc);
-    } else if (lane < 5 * NV) {
-      const int kk = lane - 4 * NV;
+    }
+    if (hrow) {
+      const int kk = lane;
       double c = 0.0, lc = 0.0;
       for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * double(vzpsi[j]);
-      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(vlampsi[j]);
+      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(vaux[2 * A2 + j]);
       static_cast<T *>(Dsrc.cpsi)[size_t(l) * NV + kk] = T(c);
       static_cast<T *>(Dsrc.lampsi)[size_t(l) * NV + kk] = T(lc);
     }
@@ -422,10 +505,10 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 
   // ---- optional outputs: trajectory and the final (alpha, d) of xi3/xi4
   if (Dsrc.traj) {
-    T *tr = static_cast<T *>(Dsrc.traj) + size_t(l) * 3 * q;
-    tr[t] = x + T(offx);
-    tr[q + t] = y + T(offy);
-    tr[2 * q + t] = psi;
+    T *trj = static_cast<T *>(Dsrc.traj) + size_t(l) * 3 * q;
+    trj[t] = x + T(offx);
+    trj[q + t] = y + T(offy);
+    trj[2 * q + t] = psi;
   }
   if (Dsrc.va) {
     T *va = static_cast<T *>(Dsrc.va) + size_t(l) * 4 * q;
@@ -443,8 +526,9 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const T ux = slack ? cc : cps, uy = slack ? ss : sps;
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < n; ++j) {
-        const T xt = x + rr[i] * ux - ox[j * q + t];
-        const T yt = y + rr[i] * uy - oy[j * q + t];
+        const Pair<T> o = oxy[j * q + t];
+        const T xt = x + rr[i] * ux - o.x;
+        const T yt = y + rr[i] * uy - o.y;
         const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
         const T al = literal_alpha ? atan2z(yt, xt) : atan2z(a * yt, b * xt);
         const T ca = Num<T>::cos_(al), sa = Num<T>::sin_(al);
@@ -456,48 +540,41 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   }
 }
 
+// One block: LDS set-up shared by the block's trajectories, then the loop.
 template <typename T, int NV, int TILE>
-__global__ __launch_bounds__(kWave * 2 * TILE) void fused_kernel(Desc single, const Desc *table, int nprob) {
+__device__ __forceinline__ void fused_block(const Desc &D) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds = reinterpret_cast<T *>(smem_raw);
-  int p = 0;
-  if (table) {
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {   // last problem whose first block is <= blockIdx.x
-      const int mid = (lo + hi + 1) >> 1;
-      if (table[mid].blk0 <= int(blockIdx.x)) lo = mid; else hi = mid - 1;
-    }
-    p = lo;
-  }
-  const Desc &D = table ? table[p] : single;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const int q = D.q, n = D.n, B = D.B, blk0 = D.blk0;
+  const int q = uni(D.q), n = uni(D.n), B = uni(D.B), blk0 = uni(D.blk0);
   const FusedLds L = fused_layout(q, n, NV, TILE);
+  constexpr int N2 = 2 * NV, A2 = pad4(N2);
 
-  // block-wide: obstacle tables (centred), inflated semi-axes, operators
+  // block-wide: obstacle tables (centred, (x, y) pairs), inflated semi-axes,
+  // operators as Quad [a2/4][2nv], zeroed per-wave areas (their padding
+  // entries are read as zeros)
   const T *gox = static_cast<const T *>(D.ox), *goy = static_cast<const T *>(D.oy);
   const T offx = T(D.offx), offy = T(D.offy), rc = T(D.rc);
-  for (int i = tid; i < n * q; i += blockDim.x) {
-    lds[L.ox + i] = gox[i] - offx;
-    lds[L.oy + i] = goy[i] - offy;
-  }
+  Pair<T> *oxy = reinterpret_cast<Pair<T> *>(lds + L.oxy);
+  for (int i = tid; i < n * q; i += blockDim.x) oxy[i] = Pair<T>{gox[i] - offx, goy[i] - offy};
   for (int j = tid; j < n; j += blockDim.x) {
     const T a = static_cast<const T *>(D.oa)[j] + rc;
     const T b = static_cast<const T *>(D.ob)[j] + rc;
     T *o = lds + L.op + j * 8;
-    o[OP_A] = a; o[OP_B] = b; o[OP_A2] = a * a; o[OP_B2] = b * b; o[OP_AB] = a * b;
-    o[OP_AMAX] = fmax(a, b);
+    o[OP_A2] = a * a; o[OP_B2] = b * b; o[OP_AB] = a * b; o[OP_AMAX] = fmax(a, b);
+    o[OP_A] = a; o[OP_B] = b; o[6] = T(0); o[7] = T(0);
   }
-  const T *gM1 = static_cast<const T *>(D.M1), *gM2 = static_cast<const T *>(D.M2),
-          *gGF = static_cast<const T *>(D.GF);
-  for (int i = tid; i < 4 * NV * NV; i += blockDim.x) {
-    lds[L.m1 + i] = gM1[i];
-    lds[L.gf + i] = gGF[i];
+  const T *gM1 = static_cast<const T *>(D.M1), *gGF = static_cast<const T *>(D.GF);
+  for (int e = tid; e < A2 * N2; e += blockDim.x) {
+    // element e of the Quad layout: chunk c, row I, component e % 4
+    const int c = e / (4 * N2), rem = e % (4 * N2), I = rem / 4, J = 4 * c + rem % 4;
+    lds[L.m1 + e] = J < N2 ? gM1[I * N2 + J] : T(0);
+    lds[L.gf + e] = J < N2 ? gGF[I * N2 + J] : T(0);
   }
-  for (int i = tid; i < NV * NV; i += blockDim.x) lds[L.m2 + i] = gM2[i];
+  for (int i = tid; i < 2 * TILE * L.wave_stride; i += blockDim.x) lds[L.wave0 + i] = T(0);
   __syncthreads();
 
-  // Both trajectories of the block run the loop (it has block-wide
+  // Every trajectory slot of the block runs the loop (it has block-wide
   // barriers); a slot past the end of the batch computes a copy of the last
   // trajectory and stores nothing.
   const int lt = (int(blockIdx.x) - blk0) * TILE + (wave >> 1);
@@ -505,16 +582,39 @@ __global__ __launch_bounds__(kWave * 2 * TILE) void fused_kernel(Desc single, co
   fused_body<T, NV>(D, live ? lt : B - 1, live, wave & 1, lds, L, lane, wave);
 }
 
+// One problem: the descriptor travels as a kernel argument.
+template <typename T, int NV, int TILE>
+__global__ __launch_bounds__(kWave * 2 * TILE) void fused_kernel(Desc single) {
+  fused_block<T, NV, TILE>(single);
+}
+
+// Several problems: block b belongs to the last problem whose first block is
+// <= b (binary search of the table in global memory).
+template <typename T, int NV, int TILE>
+__global__ __launch_bounds__(kWave * 2 * TILE) void fused_multi_kernel(const Desc *__restrict__ table, int nprob) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (uni(table[mid].blk0) <= int(blockIdx.x)) lo = mid; else hi = mid - 1;
+  }
+  fused_block<T, NV, TILE>(table[uni(lo)]);
+}
+
 template <typename T, int NV, int TILE>
 hipError_t launch_t(const Desc &single, const Desc *table, int nprob, int nblocks, hipStream_t st,
                     size_t lds_bytes) {
+  const void *fn = table ? reinterpret_cast<const void *>(&fused_multi_kernel<T, NV, TILE>)
+                         : reinterpret_cast<const void *>(&fused_kernel<T, NV, TILE>);
   if (lds_bytes > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_kernel<T, NV, TILE>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((fused_kernel<T, NV, TILE>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes, st,
-                     single, table, nprob);
+  if (table)
+    hipLaunchKernelGGL((fused_multi_kernel<T, NV, TILE>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes, st,
+                       table, nprob);
+  else
+    hipLaunchKernelGGL((fused_kernel<T, NV, TILE>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes, st,
+                       single);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ struct Desc {
   const void *M1, *H1;       // xi1: [2nv][2nv] and [2nv][6]
   const void *M2, *H2;       // xi2: [nv][nv] and [nv][6]
   const void *GF;            // [2nv][2nv] F^T F of one axis in the z basis
+  const void *Ut;            // [q][nv] U M2^T (heading rows premultiplied by M2)
   const double *R, *Rinv;    // z = R c (Bernstein c), [nv][nv]
   // problem
   const void *ox, *oy, *oa, *ob;
@@ -52,9 +53,10 @@ struct Consts {
   double *A1, *A2;               // Gauss-Jordan work [N][2N]
   double *M1, *H1, *M2, *H2, *GF;
   double *K1b_inv, *K2b_inv;     // Bernstein-space inverses (diagnostics)
+  double *Ut;                    // [q][nv] U M2^T
   double *status;                // [0]: 0 ok, 1 singular xi1 KKT, 2 singular xi2 KKT
   void *tU, *tV, *tW, *tM1, *tH1, *tM2, *tH2, *tGF;  // typed copies
-  void *tP, *tPd, *tPdd;
+  void *tP, *tPd, *tPdd, *tUt;
 };
 
 // Launchers (defined in the .hip files).

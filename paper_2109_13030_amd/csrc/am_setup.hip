@@ -292,6 +292,15 @@ __global__ __launch_bounds__(kSetupThreads) void setup_kernel(SetupArgs a) {
   }
   __syncthreads();
 
+  // U~ = U M2^T: the heading step's rows premultiplied by M2
+  for (int idx = tid; idx < q * nv; idx += kSetupThreads) {
+    const int t = idx / nv, k = idx % nv;
+    double v = 0.0;
+    for (int j = 0; j < nv; ++j) v += c.U[t * nv + j] * c.M2[k * nv + j];
+    c.Ut[idx] = v;
+  }
+  __syncthreads();
+
   // 9. Typed copies for the iteration kernels.
   if (a.f64) {
     to_typed<double>(c.U, c.tU, q * nv); to_typed<double>(c.V, c.tV, q * nv);
@@ -299,14 +308,14 @@ __global__ __launch_bounds__(kSetupThreads) void setup_kernel(SetupArgs a) {
     to_typed<double>(c.H1, c.tH1, n2 * 6); to_typed<double>(c.M2, c.tM2, nv * nv);
     to_typed<double>(c.H2, c.tH2, nv * 6); to_typed<double>(c.GF, c.tGF, n2 * n2);
     to_typed<double>(c.P, c.tP, q * nv); to_typed<double>(c.Pd, c.tPd, q * nv);
-    to_typed<double>(c.Pdd, c.tPdd, q * nv);
+    to_typed<double>(c.Pdd, c.tPdd, q * nv); to_typed<double>(c.Ut, c.tUt, q * nv);
   } else {
     to_typed<float>(c.U, c.tU, q * nv); to_typed<float>(c.V, c.tV, q * nv);
     to_typed<float>(c.W, c.tW, q * nv); to_typed<float>(c.M1, c.tM1, n2 * n2);
     to_typed<float>(c.H1, c.tH1, n2 * 6); to_typed<float>(c.M2, c.tM2, nv * nv);
     to_typed<float>(c.H2, c.tH2, nv * 6); to_typed<float>(c.GF, c.tGF, n2 * n2);
     to_typed<float>(c.P, c.tP, q * nv); to_typed<float>(c.Pd, c.tPd, q * nv);
-    to_typed<float>(c.Pdd, c.tPdd, q * nv);
+    to_typed<float>(c.Pdd, c.tPdd, q * nv); to_typed<float>(c.Ut, c.tUt, q * nv);
   }
 }
 
