@@ -10,12 +10,66 @@ namespace amk {
 template <typename T>
 struct Num;
 
+// FP32 atan2 and sincos written for the iteration kernels (fewer
+// instructions than the general library routines, which also handle huge
+// arguments).  Both use polynomial fits made for this library by iteratively
+// reweighted least squares (a near-minimax fit) on dense grids:
+//  * atan(r) = r P(r^2) on [0, 1], P of degree 8, then the octant fix-ups
+//    atan2 = pi/2 - atan(1/r), pi - ... and the sign of y; max error
+//    ~3e-7 rad including the rounding of min/max;
+//  * sin r = r + r^3 S(r^2), cos r = 1 - r^2/2 + r^4 C(r^2) on [-pi/4, pi/4],
+//    S and C of degree 3, after a two-constant Cody-Waite reduction by
+//    pi/2 with fused multiply-adds (exact for |a| < ~1e4 to ~1e-11);
+//    max error ~9e-8.
+// The zero vector is handled by atan2z, not here.
+__device__ __forceinline__ float atan2_f32(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float r = mn * __builtin_amdgcn_rcpf(mx), u = r * r;
+  float p = 0.002452445449307561f;
+  p = fmaf(p, u, -0.014384330250322819f);
+  p = fmaf(p, u, 0.03975366801023483f);
+  p = fmaf(p, u, -0.07232531905174255f);
+  p = fmaf(p, u, 0.10497856885194778f);
+  p = fmaf(p, u, -0.14160951972007751f);
+  p = fmaf(p, u, 0.19985872507095337f);
+  p = fmaf(p, u, -0.33332595229148865f);
+  p = fmaf(p, u, 0.9999998807907104f);
+  float a = r * p;
+  a = ay > ax ? 1.5707963267948966f - a : a;
+  a = x < 0.0f ? 3.141592653589793f - a : a;
+  return copysignf(a, y);
+}
+
+__device__ __forceinline__ void sincos_f32(float a, float *s, float *c) {
+  const float k = rintf(a * 0.6366197723675814f);           // nearest multiple of pi/2
+  float r = fmaf(-k, 1.5707963705062866f, a);               // pi/2 = c1 + c2
+  r = fmaf(-k, -4.371138828673793e-08f, r);
+  const float u = r * r;
+  float ps = 2.716131348279305e-06f;
+  ps = fmaf(ps, u, -0.00019839058222714812f);
+  ps = fmaf(ps, u, 0.008333328180015087f);
+  ps = fmaf(ps, u, -0.1666666716337204f);
+  const float sr = fmaf(r * u, ps, r);
+  float pc = -2.721033922625793e-07f;
+  pc = fmaf(pc, u, 2.479952308931388e-05f);
+  pc = fmaf(pc, u, -0.0013888883404433727f);
+  pc = fmaf(pc, u, 0.0416666679084301f);
+  const float cr = fmaf(u * u, pc, fmaf(-0.5f, u, 1.0f));
+  const int qd = int(k) & 3;                                 // quadrant of a
+  const float s0 = (qd & 1) ? cr : sr, c0 = (qd & 1) ? sr : cr;
+  *s = (qd & 2) ? -s0 : s0;
+  *c = ((qd + 1) & 2) ? -c0 : c0;
+}
+
 template <>
 struct Num<float> {
   static __device__ __forceinline__ float rsqrt(float x) { return rsqrtf(x); }
   static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
-  static __device__ __forceinline__ float atan2_(float y, float x) { return atan2f(y, x); }
-  static __device__ __forceinline__ void sincos_(float a, float *s, float *c) { sincosf(a, s, c); }
+  // hardware square root (about 1 ulp), for bounds that tolerate it
+  static __device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float atan2_(float y, float x) { return atan2_f32(y, x); }
+  static __device__ __forceinline__ void sincos_(float a, float *s, float *c) { sincos_f32(a, s, c); }
   static __device__ __forceinline__ float hypot_(float a, float b) { return hypotf(a, b); }
   static __device__ __forceinline__ float cos_(float a) { return cosf(a); }
   static __device__ __forceinline__ float sin_(float a) { return sinf(a); }
@@ -25,6 +79,7 @@ template <>
 struct Num<double> {
   static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
   static __device__ __forceinline__ double sqrt_(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double sqrt_fast(double x) { return ::sqrt(x); }
   static __device__ __forceinline__ double atan2_(double y, double x) { return ::atan2(y, x); }
   static __device__ __forceinline__ void sincos_(double a, double *s, double *c) { ::sincos(a, s, c); }
   static __device__ __forceinline__ double hypot_(double a, double b) { return ::hypot(a, b); }

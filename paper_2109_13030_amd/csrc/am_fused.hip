@@ -47,6 +47,7 @@ namespace {
 
 constexpr int kMaxC = AM_MAX_CIRCLES;
 constexpr int kVoteChunk = 8;   // obstacles whose positions are loaded together in the vote
+constexpr double kVoteMargin = 0.25;   // [m] slack of the near-obstacle set, see project_reduce
 
 // Wave-uniform copies of descriptor fields: the compiler then keeps them in
 // scalar registers and treats loops over them as uniform.
@@ -291,34 +292,56 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // the two waves; afterwards lane k < 4nv holds row k of the total in `tr`
   // and lane k < nv row 4nv+k in `trpsi`.
   T tr = T(0), trpsi = T(0);
+  // near-obstacle set of the last vote and the positions it was taken at
+  T xvote = T(0), yvote = T(0), extvote = T(0);
+  uint64_t near_set = 0;
+  bool voted = false;
   auto project_reduce = [&](bool with_psi) {
     const T ux = slack ? cc : cps, uy = slack ? ss : sps;
 #pragma unroll
     for (int i = 0; i < kMaxC; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
     if (!literal_alpha) {
-      // wave-wide vote: obstacles near enough to some lane's robot.  The
-      // positions of a chunk of obstacles are loaded before any is tested.
-      const T ext = rmax * Num<T>::sqrt_(ux * ux + uy * uy);
-      uint64_t near_mask = 0;
-      for (int j0 = 0; j0 < n; j0 += kVoteChunk) {
-        Pair<T> o[kVoteChunk];
-        T am[kVoteChunk];
+      // Wave-wide vote: obstacles within ext + max(a, b) + margin of some
+      // lane's robot centre, ext = max|r_i| |u| the reach of its circles.
+      // The set stays valid while every lane has moved by less than the
+      // margin minus any growth of ext since the vote (an obstacle outside
+      // it is then still farther than ext + max(a, b), where every circle
+      // is outside the ellipse and contributes exactly zero), so the vote
+      // is repeated only when some lane has moved that far.  The positions
+      // of a chunk of obstacles are loaded before any is tested.
+      // (|u| from the hardware square root, enlarged by 1e-6 so that the
+      // rounding of the estimate cannot make ext too small)
+      const T ext = rmax * Num<T>::sqrt_fast(ux * ux + uy * uy) * T(1.000001);
+      const T margin = T(kVoteMargin);
+      const T dxv = x - xvote, dyv = y - yvote, room = margin - (ext - extvote);
+      const bool stale = tv & !(room > T(0) && dxv * dxv + dyv * dyv <= room * room);
+      if (!voted || __ballot(stale) != 0) {
+        voted = true;
+        xvote = x;
+        yvote = y;
+        extvote = ext;
+        near_set = 0;
+        for (int j0 = 0; j0 < n; j0 += kVoteChunk) {
+          Pair<T> o[kVoteChunk];
+          T am[kVoteChunk];
 #pragma unroll
-        for (int k = 0; k < kVoteChunk; ++k) {
-          const int j = j0 + k < n ? j0 + k : n - 1;
-          o[k] = oxy[j * q + tt];
-          am[k] = op[j * 8 + OP_AMAX];
-        }
+          for (int k = 0; k < kVoteChunk; ++k) {
+            const int j = j0 + k < n ? j0 + k : n - 1;
+            o[k] = oxy[j * q + tt];
+            am[k] = op[j * 8 + OP_AMAX];
+          }
 #pragma unroll
-        for (int k = 0; k < kVoteChunk; ++k) {
-          const T dx = x - o[k].x, dy = y - o[k].y;
-          const T reach = ext + am[k];
-          const bool near = tv & (dx * dx + dy * dy < reach * reach);
-          const uint64_t bal = __ballot(near);
-          if (j0 + k < n && bal != 0) near_mask |= uint64_t(1) << (j0 + k);
+          for (int k = 0; k < kVoteChunk; ++k) {
+            const T dx = x - o[k].x, dy = y - o[k].y;
+            const T reach = ext + am[k] + margin;
+            const bool near = tv & (dx * dx + dy * dy < reach * reach);
+            const uint64_t bal = __ballot(near);
+            if (j0 + k < n && bal != 0) near_set |= uint64_t(1) << (j0 + k);
+          }
         }
       }
       // active obstacles, the next one's data loaded while this one is used
+      uint64_t near_mask = near_set;
       if (near_mask) {
         int j = __builtin_ctzll(near_mask);
         near_mask &= near_mask - 1;
@@ -402,12 +425,25 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     // partials of F^T (F xi - g) (x: rows 0..2nv-1, y: 2nv..4nv-1, as
     // [V W U] on the position block and U on the slack block) and of
     // U~^T (psi - psi_hat) (rows 4nv..5nv-1)
+    // (the velocity and acceleration rows are usually inside their discs on
+    // every lane of the wave; their terms are then zero and are left out)
     T pr[G];
+    if (__ballot((fv > T(0)) | (fa > T(0))) != 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        pr[k] = Vb[k] * rvx + Wb[k] * rax + Ub[k] * ro1x;
+        pr[2 * NV + k] = Vb[k] * rvy + Wb[k] * ray + Ub[k] * ro1y;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        pr[k] = Ub[k] * ro1x;
+        pr[2 * NV + k] = Ub[k] * ro1y;
+      }
+    }
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      pr[k] = Vb[k] * rvx + Wb[k] * rax + Ub[k] * ro1x;
       pr[NV + k] = Ub[k] * ro2x;
-      pr[2 * NV + k] = Vb[k] * rvy + Wb[k] * ray + Ub[k] * ro1y;
       pr[3 * NV + k] = Ub[k] * ro2y;
       pr[4 * NV + k] = Ut[k] * rp;
     }

@@ -125,19 +125,30 @@ class MPC:
     def __init__(self, batch: int, iters: int = 10, horizon: float = 10.0, q: int = 100, nv: int = 11,
                  circles: int = 5, length: float = 1.5, width: float = 0.5, n_obs: int = 30,
                  vmax: float = 1.5, amax: float = 1.5, rho: float = 1.0, sigma: float = 0.5,
-                 fc_tol: float = 0.02, seed: int = 0):
+                 fc_tol: float = 0.02, buffer: float = 0.05, reuse_previous: bool = True,
+                 dt: float = 0.04, seed: int = 0):
         import torch
         self.torch = torch
         self.B, self.K, self.tf, self.q, self.nv = int(batch), int(iters), float(horizon), int(q), int(nv)
         self.m, self.n = int(circles), int(n_obs)
         self.length, self.width = float(length), float(width)
         self.r = inputs.circle_offsets(self.m, self.length)
-        self.rc = self.width / 2.0
+        # circles that cover the rectangle: radius to the corners of each
+        # circle's L/m x W slice
+        self.rc = math.hypot(self.length / (2 * self.m), self.width / 2.0)
         self.vmax, self.amax, self.rho, self.sigma, self.fc_tol = vmax, amax, rho, sigma, fc_tol
+        self.buffer, self.reuse, self.dt = float(buffer), bool(reuse_previous), float(dt)
         self.rng = np.random.default_rng(seed)
         self.h = am.Handle(self.q, self.nv, self.tf, self.r, self.n, self.rho, dtype="f32")
         self.state = None
+        self.prev = None
         self.res = torch.empty((self.B, am.NRES), dtype=torch.float32, device="cuda")
+        # coefficients of a trajectory delayed by one period, by least squares
+        # on the grid: c' = pinv(P) P(t + dt) c
+        grid = inputs.time_grid(self.q, self.tf)
+        P = np.stack([bernstein_rows(self.nv, self.tf, t)[0] for t in grid])
+        Ps = np.stack([bernstein_rows(self.nv, self.tf, t + self.dt)[0] for t in grid])
+        self.shift = np.linalg.pinv(P) @ Ps
 
     def problem(self, crowd: Crowd, now: float, p0, v0, a0, psi0, dpsi0, ddpsi0) -> dict:
         t = inputs.time_grid(self.q, self.tf) + now
@@ -145,7 +156,8 @@ class MPC:
         oy = crowd.pos[:, 1:] + crowd.vel[:, 1:] * t[None, :]
         goal_x = crowd.start[0] + crowd.speed * (now + self.tf)
         return dict(q=self.q, nv=self.nv, tf=self.tf, r=self.r, ox=ox, oy=oy,
-                    oa=np.full(self.n, crowd.radius), ob=np.full(self.n, crowd.radius), rc=self.rc,
+                    oa=np.full(self.n, crowd.radius + self.buffer), ob=np.full(self.n, crowd.radius + self.buffer),
+                    rc=self.rc,
                     bx=np.array([p0[0], v0[0], a0[0], goal_x, crowd.speed, 0.0]),
                     by=np.array([p0[1], v0[1], a0[1], crowd.start[1], 0.0, 0.0]),
                     bpsi=np.array([psi0, dpsi0, ddpsi0, 0.0, 0.0, 0.0]),
@@ -154,11 +166,16 @@ class MPC:
     def samples(self, pb: dict) -> dict:
         """Initial coefficients: Gaussian samples around the straight line
         between the two position boundary values (Sec. IV); a batch of one
-        takes the straight line itself."""
+        takes the straight line itself.  With `reuse_previous`, sample 0 is
+        the previous period's selected trajectory delayed by one period."""
         B, nv = self.B, self.nv
         sig = self.sigma if B > 1 else 0.0
         init = inputs.make_initial(pb, B, int(self.rng.integers(1 << 31)), sig)
-        return {k: init[k] for k in ("cx", "cc", "cy", "cs", "cpsi")}
+        init = {k: init[k] for k in ("cx", "cc", "cy", "cs", "cpsi")}
+        if self.reuse and self.prev is not None:
+            for k in init:
+                init[k][0] = self.shift @ self.prev[k]
+        return init
 
     def plan(self, pb: dict):
         """One replanning period: solve, select; returns (coefficients of the
@@ -177,16 +194,19 @@ class MPC:
         idx, cost, fc = am.select_best(self.h, self.res, self.fc_tol)
         if idx < 0:
             raise RuntimeError("every trajectory of the batch is non-finite")
-        coef = {k: self.state.t[k][idx].double().cpu().numpy() for k in ("cx", "cy", "cpsi")}
+        coef = {k: self.state.t[k][idx].double().cpu().numpy() for k in ("cx", "cc", "cy", "cs", "cpsi")}
+        self.prev = coef
         ms = (time.perf_counter() - t0) * 1e3
         return coef, fc <= self.fc_tol, ms
 
-    def run(self, crowd: Crowd, duration: float = 25.0, dt: float = 0.04) -> EpisodeResult:
+    def run(self, crowd: Crowd, duration: float = 25.0) -> EpisodeResult:
         """Closed loop until the robot has covered the course or `duration`
         seconds have passed; the robot follows the selected trajectory for
         one control period dt, the people move on, collisions are checked at
         every period with the true rectangle and discs."""
         self.state = None
+        self.prev = None
+        dt = self.dt
         p = crowd.start.astype(float).copy()
         v = np.array([crowd.speed, 0.0])
         a = np.zeros(2)

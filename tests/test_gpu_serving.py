@@ -148,18 +148,20 @@ def _best_rule(res, tol):
     return -1
 
 
-def test_select_best_rule_on_planted_rows(am):
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_select_best_rule_on_planted_rows(am, dtype):
     """am_select_best on hand-made residual rows: least cost among rows under
     the collision tolerance, ties to the lower index, fallback to the least
     max |f_c|, -1 when every row is non-finite."""
     import torch
     c = _clients(1)[0]
-    h = _handles(am, [c])[0]
+    h = am.Handle.for_problem(c["problem"], dtype)
+    ft = np.float32 if dtype == "f32" else np.float64
     rng = np.random.default_rng(3)
     for B, case in ((1, "one"), (37, "ties"), (700, "fallback"), (5000, "random"), (64, "nonfinite")):
-        res = np.zeros((B, am.NRES), np.float32)
-        res[:, 0] = rng.uniform(0.0, 0.2, B).astype(np.float32)
-        res[:, 7] = np.round(rng.uniform(1.0, 5.0, B), 1).astype(np.float32)   # many equal costs
+        res = np.zeros((B, am.NRES), ft)
+        res[:, 0] = rng.uniform(0.0, 0.2, B).astype(ft)
+        res[:, 7] = np.round(rng.uniform(1.0, 5.0, B), 1).astype(ft)   # many equal costs
         if case == "fallback":
             res[:, 0] += 0.5
         if case == "nonfinite":
@@ -170,7 +172,7 @@ def test_select_best_rule_on_planted_rows(am):
             res[5:, 7] = 1.5
         t = torch.as_tensor(res, device="cuda")
         idx, cost, fc = am.select_best(h, t, 0.05)
-        want = _best_rule(res, np.float32(0.05))
+        want = _best_rule(res, ft(0.05))
         assert idx == want, case
         if case == "ties":
             assert idx == 5
