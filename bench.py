@@ -117,9 +117,9 @@ def run_gpu(args):
         last = states[-1]
         return wall, solve_ms, step_ms, last
 
-    # launch shape: the library's autotuner times each tile once per shape
-    # (setup, not timed)
-    tile, tile_ms = am.autotune(h, p, make_states(1)[0], K)
+    # launch configuration (tile, register budget): the library's autotuner
+    # times each once per shape (setup, not timed)
+    (tile, waves), tile_ms = am.autotune(h, p, make_states(1)[0], K)
     fused = lambda s: am.solve(h, p, s, K)
     wall, solve_ms, step_ms, last = timed(fused, args.steps, args.warmup)
     res = am.residuals(h, p, last).cpu().numpy()
@@ -150,9 +150,9 @@ def run_gpu(args):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
                      "traffic": measured_traffic(args.workload) if dtype == "f32" else None,
-                     "kernel": f"fused_kernel<{'float' if dtype == 'f32' else 'double'},{nv},{tile}>",
-                     "kernel_ms": avg_kernel_s * 1e3, "tile": tile,
-                     "autotune_ms": {str(k): round(v, 4) for k, v in tile_ms.items()},
+                     "kernel": f"fused_kernel<{'float' if dtype == 'f32' else 'double'},{nv},{tile},{waves}>",
+                     "kernel_ms": avg_kernel_s * 1e3, "tile": tile, "waves_per_simd": waves,
+                     "autotune_ms": {f"tile{k[0]}_waves{k[1]}": round(v, 4) for k, v in tile_ms.items()},
                      "flop_per_launch": flops,
                      "hbm_bytes_per_launch": bytes_per_launch(q, nv, m, n, B, K)},
         "step_ms_events": float(np.mean(step_ms)),
@@ -176,7 +176,7 @@ def run_gpu(args):
     return out, pb, init, K
 
 
-def run_serving(rates, n_requests: int, modes=("continuous", "plain"), n_clients: int = 32,
+def run_serving(rates, n_requests, modes=("continuous", "plain"), n_clients: int = 32,
                 saturation: int = 64, budget: int = 4 << 30, seed: int = 5):
     """Replanning workload c5 through the continuous-batching server: Poisson
     arrivals, per request B ~ U{256..2048}, n ~ U{5..30} moving obstacles,
@@ -198,7 +198,7 @@ def run_serving(rates, n_requests: int, modes=("continuous", "plain"), n_clients
     mode_ids = {"continuous": am.SERVE_CONTINUOUS, "sequential": am.SERVE_SEQUENTIAL, "plain": am.SERVE_PLAIN}
     out = {"workload": "c5: Poisson replanning requests, B ~ U{256..2048}, n ~ U{5..30} moving obstacles, "
                        f"5 circles, {K} warm-started AM iterations per request, {n_clients} robots",
-           "iterations": K, "requests_per_rate": n_requests, "budget_bytes": budget, "modes": {}}
+           "iterations": K, "budget_bytes": budget, "modes": {}}
 
     def one(mode, rate, count, rseed):
         srv = am.Server(budget, streams=4, max_per_launch=64, mode=mode_ids[mode])
@@ -243,7 +243,12 @@ def run_serving(rates, n_requests: int, modes=("continuous", "plain"), n_clients
                 "peak_bytes": st["peak_bytes"]}
 
     for mode in modes:
-        rows = [one(mode, r, n_requests, seed + int(r)) for r in rates]
+        rows = []
+        for r in rates:
+            count = n_requests(r) if callable(n_requests) else n_requests
+            rows.append(one(mode, r, count, seed + int(r)))
+            print(f"serving {mode} {r:g} Hz: p50 {rows[-1]['p50_ms']:.3f} ms p99 {rows[-1]['p99_ms']:.3f} ms",
+                  file=sys.stderr, flush=True)
         if saturation:
             rows.append(one(mode, 0, saturation, seed))
         out["modes"][mode] = rows
@@ -294,7 +299,8 @@ def run_uneven(reps: int = 3, count: int | None = None):
     t = timeit(lambda: am.solve_multi(hs, dps, sts, K, ws), reps)
     out["one_launch"] = {"s": t, "traj_iter_per_s": work / t}
     best, times = am.autotune_multi(hs, dps, mk(), K, ws)
-    out["autotune"] = {"best_tile": best, "ms_per_tile": {str(k): v for k, v in times.items()}}
+    out["autotune"] = {"best": {"tile": best[0], "waves_per_simd": best[1]},
+                       "ms": {f"tile{k[0]}_waves{k[1]}": v for k, v in times.items()}}
     t = timeit(lambda: am.solve_multi(hs, dps, sts, K, ws), reps)
     out["one_launch_tuned"] = {"s": t, "traj_iter_per_s": work / t, "tile": best}
     g = torch.cuda.CUDAGraph()
@@ -423,7 +429,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve", action="store_true",
                     help="run only the replanning (serving) workload at 50/100/200 Hz and print its JSON")
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of each Poisson run of --serve (requests = rate x seconds)")
     ap.add_argument("--uneven", action="store_true", help="run only the 64-problem uneven workload (c3)")
     ap.add_argument("--precision", action="store_true",
                     help="run only the precision workload (c4): FP32 vs BF16-split contraction, errors vs oracle")
@@ -431,6 +438,7 @@ def main():
     ap.add_argument("--mpc", action="store_true",
                     help="run only the closed-loop MPC benchmark on synthetic crowds (batch 1, 200, 1000)")
     ap.add_argument("--mpc-episodes", type=int, default=20)
+    ap.add_argument("--mpc-iters", type=int, default=10, help="AM iterations per control period")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run only a 512 MiB elementwise copy (y = x * 1), the size reference for "
                          "hardware byte counters, and exit")
@@ -461,16 +469,18 @@ def main():
 
         from paper_2109_13030_amd import mpc
         torch.cuda.set_device(0)
-        res = mpc.benchmark(episodes=args.mpc_episodes,
+        res = mpc.benchmark(episodes=args.mpc_episodes, iters=args.mpc_iters,
                             progress=lambda s: print(s, file=sys.stderr, flush=True))
         print(json.dumps({"workload": "closed-loop MPC, 30-person synthetic crowds (static, same-direction "
                                       "flow up to 0.3 m/s, opposite flow up to 1.0 m/s), 1.5x0.5 m robot "
-                                      "tracking a straight line at 1 m/s, 40 ms period, 10 warm-started "
-                                      "iterations, 10 s horizon", "episodes": args.mpc_episodes,
-                          "results": res}), flush=True)
+                                      f"tracking a straight line at 1 m/s, 40 ms period, {args.mpc_iters} "
+                                      "warm-started iterations, 10 s horizon, nearest 10 people per period",
+                          "episodes": args.mpc_episodes, "iterations": args.mpc_iters, "results": res}),
+              flush=True)
         return
     if args.serve:
-        print(json.dumps(run_serving((50.0, 100.0, 200.0), args.serve_requests, saturation=256)), flush=True)
+        print(json.dumps(run_serving((50.0, 100.0, 200.0), lambda r: int(r * args.serve_seconds), saturation=256)),
+              flush=True)
         return
     out, pb, init, K = run_gpu(args)
     if not args.no_serve:

@@ -68,9 +68,12 @@ extern "C" {
  * AM_Q_CS_ZERO      acceleration cost on the x, y blocks of xi1 only; default:
  *                   on all four blocks (Sec. III-C, "block-diagonal stacking").
  * Precision option (not a reading; AM_F32 handles only):
- * AM_PLAIN_BF16X3   the plain path forms its stacked contraction F^T(F xi - g)
- *                   with BF16 matrix-core products, FP32 accumulation and a
- *                   split correction (a_hi b_hi + a_hi b_lo + a_lo b_hi). */
+ * AM_PLAIN_BF16X3   the plain path forms its two dense contractions on the
+ *                   matrix cores: the stacked F^T(F xi - g) with BF16
+ *                   products, FP32 accumulation and a split correction
+ *                   (a_hi b_hi + a_hi b_lo + a_lo b_hi), and the xi1
+ *                   product KKT^-1 rhs (eq. zeta_1_sepration_3) with FP32
+ *                   matrix-core products. */
 #define AM_ALPHA_LITERAL  1u
 #define AM_XTILDE_SLACK   2u
 #define AM_PSI_NO_UNWRAP  4u
@@ -189,25 +192,34 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
                    const int32_t *batch, const int32_t *iters, const am_state *states,
                    void *workspace, size_t workspace_bytes, void *stream);
 
-/* Launch shape of the one-launch solve: trajectories per 2*64*tile-thread
- * block (two wavefronts per trajectory), tile in {1, 2, 4}; default 2.  A
- * multi-problem launch uses the tile of handles[0]. */
+/* Launch configuration of the one-launch solve (the arithmetic, and so the
+ * result, is the same for every configuration):
+ * - tile: trajectories per 2*64*tile-thread block (two wavefronts per
+ *   trajectory), in {1, 2, 4}; default 2;
+ * - waves: register budget, the wavefronts per SIMD the kernel is built to
+ *   fit, 2 (up to 256 VGPRs) or 3 (up to 168 VGPRs, reductions in two
+ *   passes to halve the LDS area); default 2; FP64 handles accept 2 only.
+ * A multi-problem launch uses the configuration of handles[0]. */
 int am_set_tile(am_handle *h, int32_t tile);
 int am_get_tile(const am_handle *h, int32_t *tile);
+int am_set_waves(am_handle *h, int32_t waves);
+int am_get_waves(const am_handle *h, int32_t *waves);
 
 /* Autotuner: times am_solve_batch (one warm-up and three timed launches per
- * candidate, HIP events on `stream`) for every tile on the caller's scratch
- * state -- which it overwrites -- stores the fastest tile in the handle and
- * returns it in *best_tile; times_ms (may be NULL) receives the three mean
- * times in the order 1, 2, 4.  Synchronous. */
+ * candidate, HIP events on `stream`) for every launch configuration on the
+ * caller's scratch state -- which it overwrites -- stores the fastest in the
+ * handle and returns it in *best_tile and *best_waves (either may be NULL);
+ * times_ms (may be NULL) receives six mean times, tiles 1, 2, 4 at 2 waves
+ * then at 3 waves (-1 where the dtype does not allow the configuration).
+ * Synchronous. */
 int am_autotune(am_handle *h, const am_problem *p, int32_t batch, int32_t iters, const am_state *scratch,
-                void *stream, int32_t *best_tile, float *times_ms);
-/* The same for a multi-problem launch; the chosen tile is stored in every
- * handle of the list. */
+                void *stream, int32_t *best_tile, int32_t *best_waves, float *times_ms);
+/* The same for a multi-problem launch; the chosen configuration is stored in
+ * every handle of the list. */
 int am_autotune_multi(int32_t nprob, am_handle *const *handles, const am_problem *problems,
                       const int32_t *batch, const int32_t *iters, const am_state *scratch,
                       void *workspace, size_t workspace_bytes, void *stream, int32_t *best_tile,
-                      float *times_ms);
+                      int32_t *best_waves, float *times_ms);
 
 /* Residual statistics of the current state (AM_RES_* columns), written to
  * device out[batch][AM_NRES] in the handle's dtype.  alpha and d are the

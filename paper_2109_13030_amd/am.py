@@ -28,8 +28,10 @@ EXPORTS = ("am_setup", "am_destroy", "am_last_error", "am_solve_batch", "am_plai
            "am_solve_batch_plain", "am_multi_workspace_size", "am_solve_multi", "am_residuals",
            "am_setup_matrices", "am_server_create", "am_server_submit", "am_server_wait",
            "am_server_stats", "am_server_destroy", "am_set_tile", "am_get_tile", "am_autotune",
-           "am_autotune_multi", "am_select_best", "am_server_best")
+           "am_autotune_multi", "am_select_best", "am_server_best", "am_set_waves", "am_get_waves")
 TILES = (1, 2, 4)
+WAVES = (2, 3)
+LAUNCHES = tuple((t, w) for w in WAVES for t in TILES)   # order of the autotuner's times
 SERVE_CONTINUOUS, SERVE_SEQUENTIAL, SERVE_PLAIN = 0, 1, 2
 
 
@@ -105,10 +107,13 @@ def lib():
         L.am_server_destroy.restype = None
         L.am_set_tile.argtypes = [vp, i32]
         L.am_get_tile.argtypes = [vp, ct.POINTER(i32)]
+        L.am_set_waves.argtypes = [vp, i32]
+        L.am_get_waves.argtypes = [vp, ct.POINTER(i32)]
         L.am_autotune.argtypes = [vp, ct.POINTER(Problem), i32, i32, ct.POINTER(State), vp, ct.POINTER(i32),
-                                  ct.POINTER(ct.c_float)]
+                                  ct.POINTER(i32), ct.POINTER(ct.c_float)]
         L.am_autotune_multi.argtypes = [i32, ct.POINTER(vp), ct.POINTER(Problem), ct.POINTER(i32), ct.POINTER(i32),
-                                        ct.POINTER(State), vp, sz, vp, ct.POINTER(i32), ct.POINTER(ct.c_float)]
+                                        ct.POINTER(State), vp, sz, vp, ct.POINTER(i32), ct.POINTER(i32),
+                                        ct.POINTER(ct.c_float)]
         L.am_select_best.argtypes = [vp, i32, vp, ct.c_double, vp, vp, vp]
         L.am_server_best.argtypes = [vp, ct.c_int64, ct.POINTER(i32), ct.POINTER(ct.c_double),
                                      ct.POINTER(ct.c_double)]
@@ -189,6 +194,16 @@ class Handle:
     @tile.setter
     def tile(self, t: int):
         check(lib().am_set_tile(self._h, int(t)))
+
+    @property
+    def waves(self) -> int:
+        v = ct.c_int32()
+        check(lib().am_get_waves(self._h, ct.byref(v)))
+        return v.value
+
+    @waves.setter
+    def waves(self, w: int):
+        check(lib().am_set_waves(self._h, int(w)))
 
     def matrices(self):
         """(KKT1^-1, KKT2^-1, basis[3, q, nv]) in Bernstein coordinates, FP64."""
@@ -302,13 +317,13 @@ def solve_multi(handles, problems, states, iters, workspace, stream=None):
 
 
 def autotune(h: Handle, p: DeviceProblem, scratch: DeviceState, iters: int, stream=None):
-    """Picks the fastest tile for this batch (overwrites scratch); returns
-    (best tile, {tile: ms})."""
-    best = ct.c_int32()
-    times = (ct.c_float * len(TILES))()
+    """Picks the fastest launch configuration for this batch (overwrites
+    scratch); returns ((tile, waves), {(tile, waves): ms})."""
+    bt, bw = ct.c_int32(), ct.c_int32()
+    times = (ct.c_float * len(LAUNCHES))()
     check(lib().am_autotune(h.ptr, ct.byref(p.c), scratch.B, int(iters), ct.byref(scratch.c), _stream_ptr(stream),
-                            ct.byref(best), times))
-    return best.value, dict(zip(TILES, list(times)))
+                            ct.byref(bt), ct.byref(bw), times))
+    return (bt.value, bw.value), {c: v for c, v in zip(LAUNCHES, list(times)) if v >= 0}
 
 
 def autotune_multi(handles, problems, scratch_states, iters, workspace, stream=None):
@@ -318,11 +333,11 @@ def autotune_multi(handles, problems, scratch_states, iters, workspace, stream=N
     Bs = (ct.c_int32 * k)(*[s.B for s in scratch_states])
     Ks = (ct.c_int32 * k)(*([int(iters)] * k))
     S = (State * k)(*[s.c for s in scratch_states])
-    best = ct.c_int32()
-    times = (ct.c_float * len(TILES))()
+    bt, bw = ct.c_int32(), ct.c_int32()
+    times = (ct.c_float * len(LAUNCHES))()
     check(lib().am_autotune_multi(k, H, P, Bs, Ks, S, _ptr(workspace), workspace.numel() * workspace.element_size(),
-                                  _stream_ptr(stream), ct.byref(best), times))
-    return best.value, dict(zip(TILES, list(times)))
+                                  _stream_ptr(stream), ct.byref(bt), ct.byref(bw), times))
+    return (bt.value, bw.value), {c: v for c, v in zip(LAUNCHES, list(times)) if v >= 0}
 
 
 def residuals(h: Handle, p: DeviceProblem, st: DeviceState, out=None, stream=None):

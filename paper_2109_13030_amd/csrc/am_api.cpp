@@ -22,6 +22,7 @@ struct am_handle {
   int device;
   bool f64;
   int tile = amk::kDefaultTile;   // trajectories per block of the fused kernel
+  int waves = amk::kDefaultWaves; // register budget of the fused kernel (wavefronts per SIMD)
   double *buf64;       // all FP64 constants
   void *bufT;          // typed copies
   Consts c;
@@ -136,6 +137,39 @@ int time_launches(hipStream_t s, int reps, F fn, float *ms) {
   if (rc != AM_OK) return rc;
   if (e != hipSuccess) return hip_fail(e, "timing events");
   *ms = t / float(reps);
+  return AM_OK;
+}
+
+
+// Times `solve` for every launch configuration (tile x register budget) the
+// handle's dtype allows; configs[i] = {tile, waves}.  Leaves the fastest set
+// through `apply`.
+template <typename Apply, typename Solve>
+int tune(bool f64, void *stream, Apply apply, Solve solve, int keep_tile, int keep_waves, int32_t *best_tile,
+         int32_t *best_waves, float *times_ms) {
+  int bt = keep_tile, bw = keep_waves, idx = 0;
+  float best_ms = 0.f;
+  bool any = false;
+  for (int w : amk::kWaveBudgets)
+    for (int t : amk::kTiles) {
+      const int i = idx++;
+      if (f64 && w != 2) {
+        if (times_ms) times_ms[i] = -1.f;
+        continue;
+      }
+      apply(t, w);
+      float ms = 0.f;
+      const int rc = time_launches(static_cast<hipStream_t>(stream), 3, solve, &ms);
+      if (rc != AM_OK) {
+        apply(keep_tile, keep_waves);
+        return rc;
+      }
+      if (times_ms) times_ms[i] = ms;
+      if (!any || ms < best_ms) { best_ms = ms; bt = t; bw = w; any = true; }
+    }
+  apply(bt, bw);
+  if (best_tile) *best_tile = bt;
+  if (best_waves) *best_waves = bw;
   return AM_OK;
 }
 
@@ -266,11 +300,11 @@ int am_solve_batch(am_handle *h, const am_problem *p, int32_t batch, int32_t ite
   if ((rc = check_device(h)) != AM_OK) return rc;
   if (batch == 0) return AM_OK;
   const Desc d = make_desc(h, p, batch, iters, st, h->tile);
-  const size_t lds = amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64, h->tile);
+  const size_t lds = amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64, h->tile, h->waves);
   if (lds > lds_limit())
     return fail(AM_ERR_INVALID, "problem needs %zu bytes of LDS, device allows %zu", lds, lds_limit());
   hipError_t e = amk::launch_fused(d, nullptr, 1, d.nblk, h->f64, h->shape.nv,
-                                   static_cast<hipStream_t>(stream), lds, h->tile);
+                                   static_cast<hipStream_t>(stream), lds, h->tile, h->waves);
   if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
   return AM_OK;
 }
@@ -315,7 +349,7 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
     d.blk0 = blocks;
     blocks += d.nblk;
     descs.push_back(d);
-    lds = std::max(lds, amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64, h0->tile));
+    lds = std::max(lds, amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64, h0->tile, h0->waves));
   }
   if (lds > lds_limit())
     return fail(AM_ERR_INVALID, "a problem needs %zu bytes of LDS, device allows %zu", lds, lds_limit());
@@ -324,7 +358,7 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
   Desc *table = static_cast<Desc *>(workspace);
   hipError_t e = amk::launch_desc_copy(descs.data(), nprob, table, s);
   if (e != hipSuccess) return hip_fail(e, "problem table copy");
-  e = amk::launch_fused(descs[0], table, nprob, blocks, h0->f64, h0->shape.nv, s, lds, h0->tile);
+  e = amk::launch_fused(descs[0], table, nprob, blocks, h0->f64, h0->shape.nv, s, lds, h0->tile, h0->waves);
   if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
   return AM_OK;
 }
@@ -392,59 +426,48 @@ int am_get_tile(const am_handle *h, int32_t *tile) {
   return AM_OK;
 }
 
+int am_set_waves(am_handle *h, int32_t waves) {
+  if (!h) return fail(AM_ERR_INVALID, "handle is NULL");
+  if (h->f64 && waves != 2) return fail(AM_ERR_INVALID, "FP64 handles run with a budget of 2 wavefronts per SIMD");
+  for (int w : amk::kWaveBudgets)
+    if (w == waves) {
+      h->waves = waves;
+      return AM_OK;
+    }
+  return fail(AM_ERR_INVALID, "waves must be 2 or 3, got %d", waves);
+}
+
+int am_get_waves(const am_handle *h, int32_t *waves) {
+  if (!h || !waves) return fail(AM_ERR_INVALID, "handle and waves must be non-NULL");
+  *waves = h->waves;
+  return AM_OK;
+}
+
 
 int am_autotune(am_handle *h, const am_problem *p, int32_t batch, int32_t iters, const am_state *scratch,
-                void *stream, int32_t *best_tile, float *times_ms) {
+                void *stream, int32_t *best_tile, int32_t *best_waves, float *times_ms) {
   if (!h) return fail(AM_ERR_INVALID, "handle is NULL");
-  const int keep = h->tile;
-  int best = keep;
-  float best_ms = 0.f;
-  int idx = 0;
-  for (int t : amk::kTiles) {
-    h->tile = t;
-    float ms = 0.f;
-    const int rc = time_launches(static_cast<hipStream_t>(stream), 3,
-                                 [&] { return am_solve_batch(h, p, batch, iters, scratch, stream); }, &ms);
-    if (rc != AM_OK) {
-      h->tile = keep;
-      return rc;
-    }
-    if (times_ms) times_ms[idx] = ms;
-    if (idx == 0 || ms < best_ms) { best_ms = ms; best = t; }
-    ++idx;
-  }
-  h->tile = best;
-  if (best_tile) *best_tile = best;
-  return AM_OK;
+  return tune(
+      h->f64, stream, [&](int t, int w) { h->tile = t; h->waves = w; },
+      [&] { return am_solve_batch(h, p, batch, iters, scratch, stream); }, h->tile, h->waves, best_tile, best_waves,
+      times_ms);
 }
 
 int am_autotune_multi(int32_t nprob, am_handle *const *handles, const am_problem *problems, const int32_t *batch,
                       const int32_t *iters, const am_state *scratch, void *workspace, size_t workspace_bytes,
-                      void *stream, int32_t *best_tile, float *times_ms) {
+                      void *stream, int32_t *best_tile, int32_t *best_waves, float *times_ms) {
   if (nprob < 1 || !handles) return fail(AM_ERR_INVALID, "at least one problem is needed");
   for (int k = 0; k < nprob; ++k)
     if (!handles[k]) return fail(AM_ERR_INVALID, "handle %d is NULL", k);
-  const int keep = handles[0]->tile;
-  int best = keep;
-  float best_ms = 0.f;
-  int idx = 0;
-  for (int t : amk::kTiles) {
-    handles[0]->tile = t;
-    float ms = 0.f;
-    const int rc = time_launches(static_cast<hipStream_t>(stream), 3, [&] {
-      return am_solve_multi(nprob, handles, problems, batch, iters, scratch, workspace, workspace_bytes, stream);
-    }, &ms);
-    if (rc != AM_OK) {
-      handles[0]->tile = keep;
-      return rc;
-    }
-    if (times_ms) times_ms[idx] = ms;
-    if (idx == 0 || ms < best_ms) { best_ms = ms; best = t; }
-    ++idx;
-  }
-  for (int k = 0; k < nprob; ++k) handles[k]->tile = best;
-  if (best_tile) *best_tile = best;
-  return AM_OK;
+  return tune(
+      handles[0]->f64, stream,
+      [&](int t, int w) {
+        for (int k = 0; k < nprob; ++k) { handles[k]->tile = t; handles[k]->waves = w; }
+      },
+      [&] {
+        return am_solve_multi(nprob, handles, problems, batch, iters, scratch, workspace, workspace_bytes, stream);
+      },
+      handles[0]->tile, handles[0]->waves, best_tile, best_waves, times_ms);
 }
 
 int am_plain_workspace_size(const am_handle *h, int32_t batch, size_t *bytes) {

@@ -112,9 +112,12 @@ constexpr int kXchBig = 64;
 constexpr int kXchSmall = 16;
 constexpr int kXchHalf = kXchBig + kXchSmall;
 
-// Reduction scratch: up to kRedRows rows of 32 lane-pair sums.
+// Reduction scratch: up to kRedRows rows of 32 lane-pair sums (a launch
+// built for 3 wavefronts per SIMD reduces in passes of kRedRows / 2 rows to
+// halve the area).
 constexpr int kRedRows = 56;
 constexpr int kRedRowStride = 36;
+__host__ __device__ constexpr int red_rows_for(int waves) { return waves >= 3 ? kRedRows / 2 : kRedRows; }
 
 // Pairs and quads of T with the alignment of one LDS vector access.
 template <typename T>
@@ -143,7 +146,7 @@ struct WaveLds {
   int z, rhs, zpsi, aux, red;
 };
 
-__host__ __device__ inline WaveLds wave_layout(int nv) {
+__host__ __device__ inline WaveLds wave_layout(int nv, int red_rows) {
   const int p = pad4(nv), a2 = pad4(2 * nv);
   WaveLds w;
   int o = 0;
@@ -151,11 +154,11 @@ __host__ __device__ inline WaveLds wave_layout(int nv) {
   w.rhs = o; o += 2 * a2;       // lambda + rho F^T g
   w.zpsi = o; o += p;           // heading coefficients
   w.aux = o; o += 2 * a2 + p;   // set-up and write-back staging
-  w.red = o; o += kRedRows * kRedRowStride;
+  w.red = o; o += red_rows * kRedRowStride;
   return w;
 }
 
-__host__ __device__ inline FusedLds fused_layout(int q, int n, int nv, int tile) {
+__host__ __device__ inline FusedLds fused_layout(int q, int n, int nv, int tile, int red_rows) {
   FusedLds L;
   const int a2 = pad4(2 * nv);
   int o = 0;
@@ -164,8 +167,8 @@ __host__ __device__ inline FusedLds fused_layout(int q, int n, int nv, int tile)
   L.m1 = o; o += a2 * 2 * nv;
   L.gf = o; o += a2 * 2 * nv;
   L.xch = o; o += tile * 2 * kXchHalf;
-  const WaveLds w = wave_layout(nv);
-  L.wave_stride = pad4(w.red + kRedRows * kRedRowStride);
+  const WaveLds w = wave_layout(nv, red_rows);
+  L.wave_stride = pad4(w.red + red_rows * kRedRowStride);
   L.wave0 = o; o += 2 * tile * L.wave_stride;
   L.total = o;
   return L;

@@ -73,38 +73,43 @@ __device__ __forceinline__ double lane_xor1(double v) {
   return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
 }
 
-// Sums over the 64 lanes of G <= kRedRows per-lane partials.  Lane pairs are
-// added with DPP, the 32 pair sums of partial g go to LDS row g (even lanes
-// write row g, odd lanes row g+1, so every lane stores), and lane g adds its
-// row with four interleaved accumulators.  On return lane g (g < G) holds
-// the total of partial g.
-template <typename T, int G>
+// Sums over the 64 lanes of G per-lane partials, in passes of ROWS rows.
+// Lane pairs are added with DPP, the 32 pair sums of partial g go to LDS row
+// g (even lanes write row g, odd lanes row g+1, so every lane stores), and
+// lane g adds its row with four interleaved accumulators.  On return lane g
+// (g < G) holds the total of partial g; the passes do not change the order
+// of any addition.
+template <typename T, int G, int ROWS>
 __device__ __forceinline__ T wave_sum_many(const T (&p)[G], T *red, int lane) {
-  static_assert(G <= kRedRows, "too many rows");
+  static_assert(ROWS <= kRedRows && ROWS % 2 == 0, "rows per pass");
   const int odd = lane & 1, col = lane >> 1;
-#pragma unroll
-  for (int k = 0; k < G; k += 2) {
-    const T a = p[k] + lane_xor1(p[k]);
-    if (k + 1 < G) {
-      const T b = p[k + 1] + lane_xor1(p[k + 1]);
-      red[(k + odd) * kRedRowStride + col] = odd ? b : a;
-    } else if (!odd) {
-      red[k * kRedRowStride + col] = a;
-    }
-  }
-  wave_sync();
   T s = T(0);
-  if (lane < G) {
-    const Quad<T> *row = reinterpret_cast<const Quad<T> *>(red + lane * kRedRowStride);
-    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const Quad<T> v = row[c];
-      s0 += v.a; s1 += v.b; s2 += v.c; s3 += v.d;
+  for (int g0 = 0; g0 < G; g0 += ROWS) {
+    const int end = g0 + ROWS < G ? g0 + ROWS : G;
+#pragma unroll
+    for (int k = g0; k < G && k < g0 + ROWS; k += 2) {
+      const T a = p[k] + lane_xor1(p[k]);
+      if (k + 1 < end) {
+        const T b = p[k + 1] + lane_xor1(p[k + 1]);
+        red[(k - g0 + odd) * kRedRowStride + col] = odd ? b : a;
+      } else if (!odd) {
+        red[(k - g0) * kRedRowStride + col] = a;
+      }
     }
-    s = (s0 + s1) + (s2 + s3);
+    wave_sync();
+    if (lane >= g0 && lane < end) {
+      const Quad<T> *row = reinterpret_cast<const Quad<T> *>(red + (lane - g0) * kRedRowStride);
+      T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const Quad<T> v = row[c];
+        s0 += v.a; s1 += v.b; s2 += v.c; s3 += v.d;
+      }
+      s = (s0 + s1) + (s2 + s3);
+    }
+    wave_sync();
   }
-  wave_sync();
   return s;
 }
 
@@ -127,7 +132,7 @@ __device__ __forceinline__ T row_dot(const T *op, int I, const T *v) {
   return acc0 + acc1;
 }
 
-template <typename T, int NV>
+template <typename T, int NV, int RED>
 __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds, const FusedLds &L,
                            int lane, int wave) {
   constexpr int A2 = pad4(2 * NV), N2 = 2 * NV;
@@ -154,7 +159,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   const T *op = lds + L.op;
   const Quad<T> *opq = reinterpret_cast<const Quad<T> *>(lds + L.op);
   const T *M1 = lds + L.m1, *GF = lds + L.gf;
-  const WaveLds wl = wave_layout(NV);
+  const WaveLds wl = wave_layout(NV, RED);
   T *wb = lds + L.wave0 + wave * L.wave_stride;
   T *vz = wb + wl.z, *vrhs = wb + wl.rhs, *vzpsi = wb + wl.zpsi, *vaux = wb + wl.aux;
   T *red = wb + wl.red;
@@ -447,7 +452,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       pr[3 * NV + k] = Ub[k] * ro2y;
       pr[4 * NV + k] = Ut[k] * rp;
     }
-    const T tot = wave_sum_many<T, G>(pr, red, lane);
+    const T tot = wave_sum_many<T, G, RED>(pr, red, lane);
     if (lane < G) xmine[lane] = tot;
     __syncthreads();
     if (prow) tr = exchange_sum(lane);
@@ -483,7 +488,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     T pp[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) pp[k] = Ut[k] * psih;
-    const T upsi = wave_sum_many<T, NV>(pp, red, lane);
+    const T upsi = wave_sum_many<T, NV, RED>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = upsi;
     __syncthreads();
     if (hrow) vzpsi[lane] = hpsi + mu + rho * exchange_sum(kXchBig + lane);
@@ -505,7 +510,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     T pp[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) pp[k] = Ub[k] * racc;
-    const T s = wave_sum_many<T, NV>(pp, red, lane);
+    const T s = wave_sum_many<T, NV, RED>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = s;
     __syncthreads();
     if (hrow) vaux[2 * A2 + lane] = lampsi0 - rhop * exchange_sum(kXchBig + lane);
@@ -577,13 +582,14 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 }
 
 // One block: LDS set-up shared by the block's trajectories, then the loop.
-template <typename T, int NV, int TILE>
+template <typename T, int NV, int TILE, int WAVES>
 __device__ __forceinline__ void fused_block(const Desc &D) {
+  constexpr int RED = red_rows_for(WAVES);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds = reinterpret_cast<T *>(smem_raw);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int q = uni(D.q), n = uni(D.n), B = uni(D.B), blk0 = uni(D.blk0);
-  const FusedLds L = fused_layout(q, n, NV, TILE);
+  const FusedLds L = fused_layout(q, n, NV, TILE, RED);
   constexpr int N2 = 2 * NV, A2 = pad4(N2);
 
   // block-wide: obstacle tables (centred, (x, y) pairs), inflated semi-axes,
@@ -615,71 +621,81 @@ __device__ __forceinline__ void fused_block(const Desc &D) {
   // trajectory and stores nothing.
   const int lt = (int(blockIdx.x) - blk0) * TILE + (wave >> 1);
   const bool live = lt < B;
-  fused_body<T, NV>(D, live ? lt : B - 1, live, wave & 1, lds, L, lane, wave);
+  fused_body<T, NV, RED>(D, live ? lt : B - 1, live, wave & 1, lds, L, lane, wave);
 }
 
-// One problem: the descriptor travels as a kernel argument.
-template <typename T, int NV, int TILE>
-__global__ __launch_bounds__(kWave * 2 * TILE) void fused_kernel(Desc single) {
-  fused_block<T, NV, TILE>(single);
+// One problem: the descriptor travels as a kernel argument.  WAVES is the
+// register budget: at least that many wavefronts per SIMD (1: up to 512
+// VGPRs and AGPRs, 2: up to 256, 3: up to 168).
+template <typename T, int NV, int TILE, int WAVES>
+__global__ __launch_bounds__(kWave * 2 * TILE) __attribute__((amdgpu_waves_per_eu(WAVES)))
+void fused_kernel(Desc single) {
+  fused_block<T, NV, TILE, WAVES>(single);
 }
 
 // Several problems: block b belongs to the last problem whose first block is
 // <= b (binary search of the table in global memory).
-template <typename T, int NV, int TILE>
-__global__ __launch_bounds__(kWave * 2 * TILE) void fused_multi_kernel(const Desc *__restrict__ table, int nprob) {
+template <typename T, int NV, int TILE, int WAVES>
+__global__ __launch_bounds__(kWave * 2 * TILE) __attribute__((amdgpu_waves_per_eu(WAVES)))
+void fused_multi_kernel(const Desc *__restrict__ table, int nprob) {
   int lo = 0, hi = nprob - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (uni(table[mid].blk0) <= int(blockIdx.x)) lo = mid; else hi = mid - 1;
   }
-  fused_block<T, NV, TILE>(table[uni(lo)]);
+  fused_block<T, NV, TILE, WAVES>(table[uni(lo)]);
 }
 
-template <typename T, int NV, int TILE>
+template <typename T, int NV, int TILE, int WAVES>
 hipError_t launch_t(const Desc &single, const Desc *table, int nprob, int nblocks, hipStream_t st,
                     size_t lds_bytes) {
-  const void *fn = table ? reinterpret_cast<const void *>(&fused_multi_kernel<T, NV, TILE>)
-                         : reinterpret_cast<const void *>(&fused_kernel<T, NV, TILE>);
+  const void *fn = table ? reinterpret_cast<const void *>(&fused_multi_kernel<T, NV, TILE, WAVES>)
+                         : reinterpret_cast<const void *>(&fused_kernel<T, NV, TILE, WAVES>);
   if (lds_bytes > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
     if (e != hipSuccess) return e;
   }
   if (table)
-    hipLaunchKernelGGL((fused_multi_kernel<T, NV, TILE>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes, st,
-                       table, nprob);
+    hipLaunchKernelGGL((fused_multi_kernel<T, NV, TILE, WAVES>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes,
+                       st, table, nprob);
   else
-    hipLaunchKernelGGL((fused_kernel<T, NV, TILE>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes, st,
+    hipLaunchKernelGGL((fused_kernel<T, NV, TILE, WAVES>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes, st,
                        single);
   return hipGetLastError();
 }
 
-template <typename T, int NV>
+template <typename T, int NV, int WAVES>
 hipError_t launch_tile(const Desc &single, const Desc *table, int nprob, int nblocks, hipStream_t st,
                        size_t lds_bytes, int tile) {
   switch (tile) {
-    case 1: return launch_t<T, NV, 1>(single, table, nprob, nblocks, st, lds_bytes);
-    case 2: return launch_t<T, NV, 2>(single, table, nprob, nblocks, st, lds_bytes);
-    case 4: return launch_t<T, NV, 4>(single, table, nprob, nblocks, st, lds_bytes);
+    case 1: return launch_t<T, NV, 1, WAVES>(single, table, nprob, nblocks, st, lds_bytes);
+    case 2: return launch_t<T, NV, 2, WAVES>(single, table, nprob, nblocks, st, lds_bytes);
+    case 4: return launch_t<T, NV, 4, WAVES>(single, table, nprob, nblocks, st, lds_bytes);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-size_t fused_lds_bytes(int q, int n, int nv, bool f64, int tile) {
-  return size_t(fused_layout(q, n, nv, tile).total) * (f64 ? 8 : 4);
+size_t fused_lds_bytes(int q, int n, int nv, bool f64, int tile, int waves) {
+  return size_t(fused_layout(q, n, nv, tile, red_rows_for(waves)).total) * (f64 ? 8 : 4);
 }
 
+// FP64 kernels take the default budget only, built without a wavefront
+// target (their registers do not fit 256 without spilling).
 hipError_t launch_fused(const Desc &single, const Desc *table, int nprob, int nblocks, bool f64,
-                        int nv, hipStream_t st, size_t lds_bytes, int tile) {
+                        int nv, hipStream_t st, size_t lds_bytes, int tile, int waves) {
   if (nblocks <= 0) return hipSuccess;
   if (f64) {
-    if (nv == 11) return launch_tile<double, 11>(single, table, nprob, nblocks, st, lds_bytes, tile);
-    if (nv == 8) return launch_tile<double, 8>(single, table, nprob, nblocks, st, lds_bytes, tile);
-  } else {
-    if (nv == 11) return launch_tile<float, 11>(single, table, nprob, nblocks, st, lds_bytes, tile);
-    if (nv == 8) return launch_tile<float, 8>(single, table, nprob, nblocks, st, lds_bytes, tile);
+    if (waves != 2) return hipErrorInvalidValue;
+    if (nv == 11) return launch_tile<double, 11, 1>(single, table, nprob, nblocks, st, lds_bytes, tile);
+    if (nv == 8) return launch_tile<double, 8, 1>(single, table, nprob, nblocks, st, lds_bytes, tile);
+  } else if (waves == 2) {
+    if (nv == 11) return launch_tile<float, 11, 2>(single, table, nprob, nblocks, st, lds_bytes, tile);
+    if (nv == 8) return launch_tile<float, 8, 2>(single, table, nprob, nblocks, st, lds_bytes, tile);
+  } else if (waves == 3) {
+    if (nv == 11) return launch_tile<float, 11, 3>(single, table, nprob, nblocks, st, lds_bytes, tile);
+    if (nv == 8) return launch_tile<float, 8, 3>(single, table, nprob, nblocks, st, lds_bytes, tile);
   }
   return hipErrorInvalidValue;
 }

@@ -15,6 +15,8 @@ constexpr int kWavesPerBlock = 4;  // 256-thread blocks (residual kernel)
 // (a launch shape the autotuner chooses among).
 constexpr int kTiles[] = {1, 2, 4};
 constexpr int kDefaultTile = 2;
+constexpr int kWaveBudgets[] = {2, 3};   // register budgets of the fused kernel (wavefronts per SIMD)
+constexpr int kDefaultWaves = 2;
 
 // One problem of a launch: handle constants, problem data, state, sizes.
 // Pointers to typed data (float or double) are void*; the kernel template
@@ -62,9 +64,9 @@ struct Consts {
 // Launchers (defined in the .hip files).
 hipError_t launch_setup(const am_shape &s, const double *r_dev, const Consts &c, bool f64,
                         hipStream_t st);
-size_t fused_lds_bytes(int q, int n, int nv, bool f64, int tile);
+size_t fused_lds_bytes(int q, int n, int nv, bool f64, int tile, int waves);
 hipError_t launch_fused(const Desc &single, const Desc *table, int nprob, int nblocks, bool f64,
-                        int nv, hipStream_t st, size_t lds_bytes, int tile);
+                        int nv, hipStream_t st, size_t lds_bytes, int tile, int waves);
 hipError_t launch_select_best(const void *res, int B, double tol, int32_t *idx, void *vals, bool f64,
                               hipStream_t st);
 hipError_t launch_residuals(const Desc &d, const void *P, const void *Pd, const void *Pdd, void *out,

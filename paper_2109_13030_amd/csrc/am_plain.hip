@@ -412,6 +412,50 @@ __global__ void k_contract_mfma(Desc D, Ptrs<float> w) {
   }
 }
 
+// ---- xi1 on the matrix cores (with AM_PLAIN_BF16X3): per axis the batch's
+// right-hand sides times M1^T, Z[16 traj x 2nv] = RHS[16 x 2nv] M1^T, as
+// 16 x 16 output tiles over k steps of 4 (2nv padded to a multiple of 4)
+// with v_mfma_f32_16x16x4_f32: FP32 operands and accumulation.  (The BF16
+// split used for the contraction is not accurate enough here: z = M1 rhs
+// cancels large terms of rhs, and the split's 2^-17 relative product error
+// moved the final trajectories by ~1e-3 m on c4.)  Lane L supplies
+// A[traj L%16][k L/16] and B[k L/16][out L%16] and receives
+// D[traj 4(L/16)+i][out L%16].  One wavefront per 16 trajectories and axis.
+template <int NV>
+__global__ void k_xi1_mfma(Desc D, Ptrs<float> w) {
+  constexpr int N2 = 2 * NV;
+  static_assert(N2 <= 32, "two 16-wide tiles");
+  const int lane = threadIdx.x & 63;
+  const int task = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int tiles = (D.B + 15) / 16;
+  if (task >= 2 * tiles) return;
+  const int axis = task / tiles, l0 = (task % tiles) * 16, B = D.B;
+  const int r = lane & 15, kk = lane >> 4;
+  const int la = l0 + r;
+  const float *M1 = static_cast<const float *>(D.M1), *H1 = static_cast<const float *>(D.H1);
+  const double *bb = axis == 0 ? D.bx : D.by;
+  const double off = axis == 0 ? D.offx : D.offy;
+  for (int n0 = 0; n0 < N2; n0 += 16) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int out = n0 + r;
+    for (int k0 = 0; k0 < N2; k0 += 4) {
+      const int k = k0 + kk;
+      const float av = (la < B && k < N2) ? w.rhs[size_t(la) * 4 * NV + axis * N2 + k] : 0.f;
+      const float bv = (out < N2 && k < N2) ? M1[out * N2 + k] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+    }
+    if (out < N2) {
+      float h = 0.f;
+      for (int e = 0; e < 6; ++e) h += H1[out * 6 + e] * float((e == 0 || e == 3) ? bb[e] - off : bb[e]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int lt = l0 + kk * 4 + i;
+        if (lt < B) w.z[size_t(lt) * 4 * NV + axis * N2 + out] = acc[i] + h;
+      }
+    }
+  }
+}
+
 // ---- multipliers and the next right-hand side from the contraction totals
 template <typename T, int NV>
 __global__ void k_update(Desc D, Ptrs<T> w, int update) {
@@ -491,6 +535,18 @@ void contract(const Desc &D, const Ptrs<T> &w, hipStream_t st, int update) {
 }
 
 template <typename T, int NV>
+void xi1(const Desc &D, const Ptrs<T> &w, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    if (D.flags & AM_PLAIN_BF16X3) {
+      const int tasks = 2 * ((D.B + 15) / 16);
+      hipLaunchKernelGGL((k_xi1_mfma<NV>), dim3((tasks + 3) / 4), dim3(kThreads), 0, st, D, w);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_xi1<T, NV>), dim3(blocks_for(size_t(D.B) * 4 * NV)), dim3(kThreads), 0, st, D, w);
+}
+
+template <typename T, int NV>
 hipError_t run(const Desc &D, void *ws, hipStream_t st) {
   const PlainWs L = plain_layout(D.B, D.q, NV, D.m, D.n);
   const Ptrs<T> w = ptrs_of<T>(ws, L);
@@ -505,7 +561,7 @@ hipError_t run(const Desc &D, void *ws, hipStream_t st) {
   hipLaunchKernelGGL((k_targets<T>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
   contract<T, NV>(D, w, st, 0);
   for (int it = 0; it < D.K; ++it) {
-    hipLaunchKernelGGL((k_xi1<T, NV>), dim3(blocks_for(size_t(B) * 4 * NV)), dim3(kThreads), 0, st, D, w);
+    xi1<T, NV>(D, w, st);
     hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_xi2<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(nproj)), dim3(kThreads), 0, st, D, w);

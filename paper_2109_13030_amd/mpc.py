@@ -44,8 +44,8 @@ class Crowd:
 
 
 def crowd_scene(kind: str, seed: int, n: int = 30, radius: float = 0.3, speed: float = 1.0,
-                length: float = 1.5, width: float = 0.5, lane_half_width: float = 3.0,
-                extent: float = 30.0) -> Crowd:
+                length: float = 1.5, width: float = 0.5, lane_half_width: float = 4.0,
+                extent: float = 36.0) -> Crowd:
     """Seeded stand-in for the paper's crowd benchmarks: n people in a
     corridor |y| <= lane_half_width ahead of the robot (x in [4, extent]),
     at least 2 radii apart.  `same_direction`: velocities along +x with
@@ -123,7 +123,7 @@ class MPC:
     (its multipliers are the warm start)."""
 
     def __init__(self, batch: int, iters: int = 10, horizon: float = 10.0, q: int = 100, nv: int = 11,
-                 circles: int = 5, length: float = 1.5, width: float = 0.5, n_obs: int = 30,
+                 circles: int = 5, length: float = 1.5, width: float = 0.5, n_obs: int = 10,
                  vmax: float = 1.5, amax: float = 1.5, rho: float = 1.0, sigma: float = 0.5,
                  fc_tol: float = 0.02, buffer: float = 0.05, reuse_previous: bool = True,
                  dt: float = 0.04, seed: int = 0):
@@ -150,16 +150,45 @@ class MPC:
         Ps = np.stack([bernstein_rows(self.nv, self.tf, t + self.dt)[0] for t in grid])
         self.shift = np.linalg.pinv(P) @ Ps
 
+    def end_point(self, crowd: Crowd, t_end: float):
+        """End of the plan: the desired point at t_end, moved sideways in
+        0.25 m steps to the nearest spot whose body-length disc is clear of
+        every person predicted at t_end (the boundary conditions are hard
+        constraints, so the end point itself must be free)."""
+        x = crowd.start[0] + crowd.speed * t_end
+        people = crowd.pos + crowd.vel * t_end
+        need = crowd.radius + self.buffer + 0.5 * math.hypot(self.length, self.width) + 0.1
+        for dy in sorted(np.arange(-12, 13) * 0.25, key=abs):
+            y = crowd.start[1] + dy
+            if np.all(np.hypot(people[:, 0] - x, people[:, 1] - y) >= need):
+                return x, y
+        return x, crowd.start[1]
+
+    def nearest_people(self, crowd: Crowd, now: float, p0, t) -> np.ndarray:
+        """The n_obs people that come closest, over the horizon, to the
+        segment from the robot to the end of the desired line (the others
+        stay out of the problem; n_obs fixes the KKT family)."""
+        a = np.asarray(p0, float)
+        b = crowd.start + np.array([crowd.speed * (now + self.tf), 0.0])
+        ab = b - a
+        L2 = max(float(ab @ ab), 1e-12)
+        px = crowd.pos[:, 0:1] + crowd.vel[:, 0:1] * t[None, :]
+        py = crowd.pos[:, 1:2] + crowd.vel[:, 1:2] * t[None, :]
+        s = np.clip(((px - a[0]) * ab[0] + (py - a[1]) * ab[1]) / L2, 0.0, 1.0)
+        d = np.hypot(px - (a[0] + s * ab[0]), py - (a[1] + s * ab[1])).min(axis=1)
+        return np.argsort(d, kind="stable")[: self.n]
+
     def problem(self, crowd: Crowd, now: float, p0, v0, a0, psi0, dpsi0, ddpsi0) -> dict:
         t = inputs.time_grid(self.q, self.tf) + now
-        ox = crowd.pos[:, :1] + crowd.vel[:, :1] * t[None, :]
-        oy = crowd.pos[:, 1:] + crowd.vel[:, 1:] * t[None, :]
-        goal_x = crowd.start[0] + crowd.speed * (now + self.tf)
+        sel = self.nearest_people(crowd, now, p0, t)
+        ox = crowd.pos[sel, :1] + crowd.vel[sel, :1] * t[None, :]
+        oy = crowd.pos[sel, 1:] + crowd.vel[sel, 1:] * t[None, :]
+        goal_x, goal_y = self.end_point(crowd, now + self.tf)
         return dict(q=self.q, nv=self.nv, tf=self.tf, r=self.r, ox=ox, oy=oy,
                     oa=np.full(self.n, crowd.radius + self.buffer), ob=np.full(self.n, crowd.radius + self.buffer),
                     rc=self.rc,
                     bx=np.array([p0[0], v0[0], a0[0], goal_x, crowd.speed, 0.0]),
-                    by=np.array([p0[1], v0[1], a0[1], crowd.start[1], 0.0, 0.0]),
+                    by=np.array([p0[1], v0[1], a0[1], goal_y, 0.0, 0.0]),
                     bpsi=np.array([psi0, dpsi0, ddpsi0, 0.0, 0.0, 0.0]),
                     vmax=self.vmax, amax=self.amax, rho=self.rho, rho_psi=self.rho, flags=0)
 

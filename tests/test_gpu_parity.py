@@ -310,26 +310,31 @@ def test_bf16x3_plain_c4_sampled_against_oracle():
 
 # ------------------------------------------------------------- launch tiles and the autotuner
 
-def test_tiles_give_identical_results_and_autotune_picks_one():
-    """Every launch tile (trajectories per block) computes the same
-    trajectories bit for bit (ragged last block included); the autotuner
-    picks one of them and leaves it set on the handle."""
+def test_launch_configurations_give_identical_results_and_autotune_picks_one():
+    """Every launch configuration (trajectories per block x register budget)
+    computes the same trajectories bit for bit (ragged last block included);
+    the autotuner picks one of them and leaves it set on the handle."""
     import torch
     from paper_2109_13030_amd import am
     pb, init = inputs.workload("c2", batch=9)
     h = am.Handle.for_problem(pb, "f32")
     p = am.DeviceProblem(pb, "f32")
     outs = {}
-    for t in am.TILES:
-        h.tile = t
+    for t, w in am.LAUNCHES:
+        h.tile, h.waves = t, w
         st = am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32")
         am.solve(h, p, st, 15)
         torch.cuda.synchronize()
-        outs[t] = st.numpy()
-    for t in am.TILES[1:]:
+        outs[(t, w)] = st.numpy()
+    first = am.LAUNCHES[0]
+    for c in am.LAUNCHES[1:]:
         for k in ("cx", "cy", "cpsi", "lam", "lam_psi", "traj"):
-            np.testing.assert_array_equal(outs[t][k], outs[1][k])
+            np.testing.assert_array_equal(outs[c][k], outs[first][k])
     scratch = am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32")
     best, times = am.autotune(h, p, scratch, 15)
-    assert best in am.TILES and h.tile == best
-    assert all(v > 0 for v in times.values())
+    assert best in am.LAUNCHES and (h.tile, h.waves) == best
+    assert set(times) == set(am.LAUNCHES) and all(v > 0 for v in times.values())
+    # FP64 handles have the 2-wavefront budget only
+    h64 = am.Handle.for_problem(pb, "f64")
+    with pytest.raises(am.AmError):
+        h64.waves = 3
