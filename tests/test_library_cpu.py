@@ -71,6 +71,14 @@ def test_null_arguments_rejected(amlib):
     assert L.am_multi_workspace_size(3, ct.byref(v)) == amlib.AM_OK and v.value >= 3 * 400
     assert L.am_solve_multi(0, None, None, None, None, None, None, 0, None) == amlib.AM_OK
     assert L.am_solve_multi(2, None, None, None, None, None, None, 0, None) == amlib.AM_ERR_INVALID
+    i = ct.c_int32()
+    assert L.am_set_tile(None, 2) == amlib.AM_ERR_INVALID
+    assert L.am_set_waves(None, 2) == amlib.AM_ERR_INVALID
+    assert L.am_get_waves(None, ct.byref(i)) == amlib.AM_ERR_INVALID
+    assert L.am_autotune(None, None, 1, 1, None, None, None, None, None) == amlib.AM_ERR_INVALID
+    assert L.am_autotune_multi(0, None, None, None, None, None, None, 0, None, None, None, None) == amlib.AM_ERR_INVALID
+    assert L.am_select_best(None, 1, None, 0.1, None, None, None) == amlib.AM_ERR_INVALID
+    assert L.am_server_best(None, 0, ct.byref(i), None, None) == amlib.AM_ERR_INVALID
     L.am_destroy(None)
 
 
