@@ -279,7 +279,11 @@ typedef struct {
 
 /* One solve request.  Host arrays are copied during am_server_submit. */
 typedef struct {
-  am_handle *handle;            /* shape of this request (q, nv, m, n, rho, flags)      */
+  am_handle *handle;            /* shape of this request (q, nv, m, n, rho, flags), or
+                                   NULL: then `shape` is used and the server takes the
+                                   handle from its KKT cache (one am_setup per distinct
+                                   shape, kept until am_server_destroy)                 */
+  const am_shape *shape;        /* host; read when handle is NULL                       */
   int32_t client;               /* warm-start key, >= 0                                 */
   int32_t batch;                /* trajectories, >= 1                                   */
   int32_t iters;                /* AM iterations, >= 0                                  */

@@ -66,7 +66,8 @@ class ServerConfig(ct.Structure):
 
 
 class Request(ct.Structure):
-    _fields_ = [("handle", ct.c_void_p), ("client", ct.c_int32), ("batch", ct.c_int32), ("iters", ct.c_int32),
+    _fields_ = [("handle", ct.c_void_p), ("shape", ct.POINTER(Shape)), ("client", ct.c_int32),
+                ("batch", ct.c_int32), ("iters", ct.c_int32),
                 ("obs_x", ct.POINTER(ct.c_double)), ("obs_y", ct.POINTER(ct.c_double)),
                 ("obs_a", ct.POINTER(ct.c_double)), ("obs_b", ct.POINTER(ct.c_double)),
                 ("r_circle", ct.c_double), ("bc_x", ct.c_double * 6), ("bc_y", ct.c_double * 6),
@@ -376,9 +377,27 @@ class Server:
         self._s = s
         self._meta = {}
 
-    def submit(self, h: Handle, pb: dict, client: int, batch: int, iters: int, init=None) -> int:
+    def submit(self, h, pb: dict, client: int, batch: int, iters: int, init=None) -> int:
+        """Queues a request; with h = None the server takes the handle for
+        the problem's shape from its KKT cache."""
         r = Request()
-        r.handle, r.client, r.batch, r.iters = h.ptr, int(client), int(batch), int(iters)
+        keep_shape = None
+        if h is None:
+            roff = np.ascontiguousarray(np.asarray(pb["r"], np.float64))
+            sh = Shape()
+            sh.q, sh.nv, sh.tf, sh.m = int(pb["q"]), int(pb["nv"]), float(pb["tf"]), len(roff)
+            sh.r_off = roff.ctypes.data_as(ct.POINTER(ct.c_double))
+            sh.n_obs, sh.rho = len(pb["oa"]), float(pb["rho"])
+            sh.rho_psi = float(pb.get("rho_psi", pb["rho"]))
+            sh.dtype = AM_F64 if self.dtype == "f64" else AM_F32
+            sh.flags = int(pb.get("flags", 0))
+            keep_shape = (roff, sh)
+            r.handle, r.shape = None, ct.pointer(sh)
+            nv, q = sh.nv, sh.q
+        else:
+            r.handle = h.ptr
+            nv, q = h.nv, h.q
+        r.client, r.batch, r.iters = int(client), int(batch), int(iters)
         dp = ct.POINTER(ct.c_double)
         keep = [np.ascontiguousarray(np.asarray(pb[k], np.float64)) for k in ("ox", "oy", "oa", "ob")]
         r.obs_x, r.obs_y, r.obs_a, r.obs_b = (a.ctypes.data_as(dp) for a in keep)
@@ -389,14 +408,14 @@ class Server:
         r.v_max, r.a_max = float(pb["vmax"]), float(pb["amax"])
         ini = None
         if init is not None:
-            nv = h.nv
             z = np.zeros((batch, nv))
             ini = np.ascontiguousarray(np.stack([np.asarray(init.get(k, z), np.float64)
                                                  for k in ("cx", "cc", "cy", "cs", "cpsi")], 1))
             r.init = ini.ctypes.data_as(dp)
         t = ct.c_int64()
         check(lib().am_server_submit(self._s, ct.byref(r), ct.byref(t)))
-        self._meta[t.value] = (batch, h.q)
+        del keep_shape
+        self._meta[t.value] = (batch, q)
         return t.value
 
     def wait(self, ticket: int, timeout: float = -1.0, traj: bool = False):

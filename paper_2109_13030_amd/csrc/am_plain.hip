@@ -190,44 +190,60 @@ __global__ void k_xi2(Desc D, Ptrs<T> w) {
   }
 }
 
-// ---- xi3/xi4: alpha_ij, d_ij for every (l, i, j, t); alpha_v, d_v, alpha_a, d_a
+// ---- xi3/xi4: alpha_ij, d_ij for every (l, i, j, t); alpha_v, d_v, alpha_a, d_a.
+// One wavefront per row: rows 0 .. B m n - 1 are (l, i j), rows B m n ..
+// B m n + B - 1 the velocity/acceleration pairs of trajectory l; lanes run
+// over t (t = lane, lane + 64, ...), so the row indices are wave-uniform and
+// every store is a contiguous run of the row.
+constexpr int kRowsPerBlock = kThreads / 64;
+
 template <typename T>
 __global__ void k_project(Desc D, Ptrs<T> w) {
-  const size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int q = D.q, m = D.m, n = D.n;
-  const size_t nobs = size_t(D.B) * m * n * q;
+  const int lane = threadIdx.x & 63;
+  const int row = int(blockIdx.x) * kRowsPerBlock + int(threadIdx.x) / 64;
+  const int q = D.q, m = D.m, n = D.n, mn = m * n, B = D.B;
   const bool slack = D.flags & AM_XTILDE_SLACK, literal = D.flags & AM_ALPHA_LITERAL;
-  if (g < nobs) {
-    const int t = int(g % q);
-    const size_t row = g / q;           // l * m n + (i n + j)
-    const int ij = int(row % (size_t(m) * n)), i = ij / n, j = ij % n;
-    const int l = int(row / (size_t(m) * n));
+  if (row < B * mn) {
+    const int l = row / mn, ij = row - l * mn, i = ij / n, j = ij - i * n;
     const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
-    const T ux = slack ? tr[3 * q + t] : p3[q + t], uy = slack ? tr[7 * q + t] : p3[2 * q + t];
     const T ri = T(D.r[i]);
-    const T xt = tr[t] + ri * ux - (static_cast<const T *>(D.ox)[j * q + t] - T(D.offx));
-    const T yt = tr[4 * q + t] + ri * uy - (static_cast<const T *>(D.oy)[j * q + t] - T(D.offy));
     const T a = static_cast<const T *>(D.oa)[j] + T(D.rc), b = static_cast<const T *>(D.ob)[j] + T(D.rc);
-    const T al = literal ? atan2z(yt, xt) : atan2z(a * yt, b * xt);
-    T sa, ca;
-    Num<T>::sincos_(al, &sa, &ca);
-    const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
-    w.alpha[g] = al;
-    w.d[g] = dd;
-  } else if (g < nobs + size_t(D.B) * q) {
-    const size_t h = g - nobs;
-    const int l = int(h / q), t = int(h % q);
+    const T *gox = static_cast<const T *>(D.ox) + size_t(j) * q, *goy = static_cast<const T *>(D.oy) + size_t(j) * q;
+    T *oal = w.alpha + size_t(row) * q, *od = w.d + size_t(row) * q;
+    for (int t = lane; t < q; t += 64) {
+      const T ux = slack ? tr[3 * q + t] : p3[q + t], uy = slack ? tr[7 * q + t] : p3[2 * q + t];
+      const T xt = tr[t] + ri * ux - (gox[t] - T(D.offx));
+      const T yt = tr[4 * q + t] + ri * uy - (goy[t] - T(D.offy));
+      T al, dd;
+      if (!literal) {
+        // elliptic angle: the point (a d cos al, b d sin al) is (xt, yt)
+        // itself, so d = sqrt(xt^2/a^2 + yt^2/b^2) (eq. compute_zeta_3)
+        al = atan2z(a * yt, b * xt);
+        dd = fmax(T(1), Num<T>::sqrt_(xt * xt / (a * a) + yt * yt / (b * b)));
+      } else {
+        al = atan2z(yt, xt);
+        T sa, ca;
+        Num<T>::sincos_(al, &sa, &ca);
+        dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
+      }
+      oal[t] = al;
+      od[t] = dd;
+    }
+  } else if (row < B * mn + B) {
+    const int l = row - B * mn;
     const T *tr = w.traj8 + size_t(l) * 8 * q;
-    const T xd = tr[q + t], yd = tr[5 * q + t], xdd = tr[2 * q + t], ydd = tr[6 * q + t];
-    const T av = atan2z(yd, xd), aa = atan2z(ydd, xdd);
-    T sv, cv, sa, ca;
-    Num<T>::sincos_(av, &sv, &cv);
-    Num<T>::sincos_(aa, &sa, &ca);
-    T *o = w.va4 + size_t(l) * 4 * q + t;
-    o[0] = av;
-    o[q] = fmin(T(1), fmax(T(0), (xd * cv + yd * sv) / T(D.vmax)));
-    o[2 * q] = aa;
-    o[3 * q] = fmin(T(1), fmax(T(0), (xdd * ca + ydd * sa) / T(D.amax)));
+    T *o = w.va4 + size_t(l) * 4 * q;
+    for (int t = lane; t < q; t += 64) {
+      const T xd = tr[q + t], yd = tr[5 * q + t], xdd = tr[2 * q + t], ydd = tr[6 * q + t];
+      const T av = atan2z(yd, xd), aa = atan2z(ydd, xdd);
+      T sv, cv, sa, ca;
+      Num<T>::sincos_(av, &sv, &cv);
+      Num<T>::sincos_(aa, &sa, &ca);
+      o[t] = av;
+      o[q + t] = fmin(T(1), fmax(T(0), (xd * cv + yd * sv) / T(D.vmax)));
+      o[2 * q + t] = aa;
+      o[3 * q + t] = fmin(T(1), fmax(T(0), (xdd * ca + ydd * sa) / T(D.amax)));
+    }
   }
 }
 
@@ -247,6 +263,7 @@ __global__ void k_targets(Desc D, Ptrs<T> w) {
   for (int i = 0; i < m; ++i) {
     const T ri = T(D.r[i]);
     T sx = 0, sy = 0;
+#pragma unroll 4
     for (int j = 0; j < n; ++j) {
       const size_t e = size_t(i * n + j) * q + t;
       const T a = static_cast<const T *>(D.oa)[j] + T(D.rc), b = static_cast<const T *>(D.ob)[j] + T(D.rc);
@@ -551,20 +568,20 @@ hipError_t run(const Desc &D, void *ws, hipStream_t st) {
   const PlainWs L = plain_layout(D.B, D.q, NV, D.m, D.n);
   const Ptrs<T> w = ptrs_of<T>(ws, L);
   const int B = D.B, q = D.q;
-  const size_t nproj = size_t(B) * D.m * D.n * q + size_t(B) * q;
+  const int proj_blocks = int((size_t(B) * D.m * D.n + B + kRowsPerBlock - 1) / kRowsPerBlock);
   const int wave_blocks = (B + 3) / 4;
   hipLaunchKernelGGL((k_enter<T, NV>), dim3(blocks_for(size_t(B) * 5 * NV)), dim3(kThreads), 0, st, D, w);
   // step 1: initial xi3, xi4 from the given trajectories
   hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
   hipLaunchKernelGGL((k_eval_psi<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
-  hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(nproj)), dim3(kThreads), 0, st, D, w);
+  hipLaunchKernelGGL((k_project<T>), dim3(proj_blocks), dim3(kThreads), 0, st, D, w);
   hipLaunchKernelGGL((k_targets<T>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
   contract<T, NV>(D, w, st, 0);
   for (int it = 0; it < D.K; ++it) {
     xi1<T, NV>(D, w, st);
     hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_xi2<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w);
-    hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(nproj)), dim3(kThreads), 0, st, D, w);
+    hipLaunchKernelGGL((k_project<T>), dim3(proj_blocks), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_targets<T>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
     contract<T, NV>(D, w, st, 1);
   }

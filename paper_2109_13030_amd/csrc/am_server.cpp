@@ -144,6 +144,10 @@ struct am_server {
   bool stop = false;
   std::string error;
   std::thread worker;
+  // KKT cache: handles built for requests that name a shape instead of a
+  // handle, keyed by every field that fixes the KKT and the kernels
+  std::mutex cache_mu;
+  std::map<std::string, am_handle *> kkt_cache;
 
   void *ptr(const Block &b) const { return base + b.off; }
   bool alloc_evicting(size_t bytes, int keep_client, size_t *off);
@@ -440,16 +444,37 @@ int am_server_create(const am_server_config *cfg, am_server **out) {
 }
 
 int am_server_submit(am_server *s, const am_request *r, int64_t *ticket) {
+  const auto t_submit = Clock::now();   // latency includes a KKT build on a cache miss
   if (!s || !r || !ticket) return srv_fail(AM_ERR_INVALID, "NULL argument");
-  if (!r->handle || r->client < 0 || r->batch < 1 || r->iters < 0)
-    return srv_fail(AM_ERR_INVALID, "request needs a handle, client >= 0, batch >= 1, iters >= 0");
+  if ((!r->handle && !r->shape) || r->client < 0 || r->batch < 1 || r->iters < 0)
+    return srv_fail(AM_ERR_INVALID, "request needs a handle or a shape, client >= 0, batch >= 1, iters >= 0");
+  am_handle *handle = r->handle;
+  if (!handle) {
+    const am_shape &sh = *r->shape;
+    if (sh.dtype != s->cfg.dtype) return srv_fail(AM_ERR_INVALID, "shape dtype differs from the server's");
+    if (sh.m < 1 || sh.m > AM_MAX_CIRCLES || !sh.r_off) return srv_fail(AM_ERR_INVALID, "bad circle offsets");
+    std::string key;
+    auto put = [&](const void *p, size_t n) { key.append(static_cast<const char *>(p), n); };
+    put(&sh.q, sizeof sh.q); put(&sh.nv, sizeof sh.nv); put(&sh.tf, sizeof sh.tf); put(&sh.m, sizeof sh.m);
+    put(sh.r_off, sizeof(double) * size_t(sh.m)); put(&sh.n_obs, sizeof sh.n_obs); put(&sh.rho, sizeof sh.rho);
+    put(&sh.rho_psi, sizeof sh.rho_psi); put(&sh.dtype, sizeof sh.dtype); put(&sh.flags, sizeof sh.flags);
+    std::lock_guard<std::mutex> lk(s->cache_mu);
+    auto it = s->kkt_cache.find(key);
+    if (it != s->kkt_cache.end()) {
+      handle = it->second;
+    } else {
+      const int rc = am_setup(&sh, &handle);
+      if (rc != AM_OK) return rc;   // am_setup recorded the message
+      s->kkt_cache.emplace(key, handle);
+    }
+  }
   auto req = std::make_unique<Request>();
-  req->h = r->handle;
+  req->h = handle;
   req->client = r->client;
   req->B = r->batch;
   req->K = r->iters;
-  const int q = amk::handle_q(r->handle), nv = amk::handle_nv(r->handle), n = amk::handle_n(r->handle);
-  if (amk::handle_dtype(r->handle) != s->cfg.dtype) return srv_fail(AM_ERR_INVALID, "handle dtype differs from the server's");
+  const int q = amk::handle_q(handle), nv = amk::handle_nv(handle), n = amk::handle_n(handle);
+  if (amk::handle_dtype(handle) != s->cfg.dtype) return srv_fail(AM_ERR_INVALID, "handle dtype differs from the server's");
   if (n > 0 && (!r->obs_x || !r->obs_y || !r->obs_a || !r->obs_b))
     return srv_fail(AM_ERR_INVALID, "obstacle arrays are NULL");
   req->q = q; req->nv = nv; req->n = n;
@@ -466,11 +491,11 @@ int am_server_submit(am_server *s, const am_request *r, int64_t *ticket) {
   req->prob.a_max = r->a_max;
   const size_t es = elem_size(s->cfg.dtype);
   size_t wb = 0;
-  if (s->cfg.mode == AM_SERVE_PLAIN) am_plain_workspace_size(r->handle, r->batch, &wb);
+  if (s->cfg.mode == AM_SERVE_PLAIN) am_plain_workspace_size(handle, r->batch, &wb);
   const size_t need = round_up(state_elems(r->batch, nv, q) * es) + round_up(table_elems(n, q) * es) + round_up(wb);
   if (need > s->arena.capacity())
     return srv_fail(AM_ERR_INVALID, "request needs more device memory than the server budget");
-  req->t_submit = Clock::now();
+  req->t_submit = t_submit;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return srv_fail(AM_ERR_INVALID, "server is stopping");
@@ -549,6 +574,7 @@ void am_server_destroy(am_server *s) {
     if (sl.pinned) (void)hipHostFree(sl.pinned);
   }
   if (s->base) (void)hipFree(s->base);
+  for (auto &kv : s->kkt_cache) am_destroy(kv.second);
   delete s;
 }
 

@@ -205,3 +205,24 @@ def test_server_reports_the_best_trajectory(am):
         assert idx == want
         assert cost == pytest.approx(float(r[want, 7]), rel=0, abs=0)
         assert fc == pytest.approx(float(r[want, 0]), rel=0, abs=0)
+
+
+def test_server_kkt_cache_by_shape(am):
+    """Requests that name a shape instead of a handle get a handle from the
+    server's KKT cache (one per distinct shape); results equal the direct
+    solve with a handle built for the same shape."""
+    import torch
+    clients = _clients(6)
+    K = 8
+    s = am.Server(1 << 28, streams=2, max_per_launch=8)
+    tickets = [s.submit(None, c["problem"], i, c["batch"], K, c["init"]) for i, c in enumerate(clients)]
+    outs = [s.wait(tk, 60.0, traj=True) for tk in tickets]
+    s.close()
+    assert all(o[0] for o in outs)
+    for c, (_, _, traj) in zip(clients, outs):
+        h = am.Handle.for_problem(c["problem"], "f32")
+        p = am.DeviceProblem(c["problem"], "f32")
+        ds = am.DeviceState(c["init"], 5, c["n"], c["problem"]["q"], "f32")
+        am.solve(h, p, ds, K)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ds.t["traj"].cpu().numpy(), traj)
