@@ -190,55 +190,89 @@ __global__ void k_xi2(Desc D, Ptrs<T> w) {
   }
 }
 
-// ---- xi3/xi4: alpha_ij, d_ij for every (l, i, j, t); alpha_v, d_v, alpha_a, d_a.
-// One wavefront per row: rows 0 .. B m n - 1 are (l, i j), rows B m n ..
-// B m n + B - 1 the velocity/acceleration pairs of trajectory l; lanes run
-// over t (t = lane, lane + 64, ...), so the row indices are wave-uniform and
-// every store is a contiguous run of the row.
-constexpr int kRowsPerBlock = kThreads / 64;
+// The projection and target kernels work on "items" of a trajectory l: the
+// pairs (i, t) = (k / q, k % q) for k < m q, each looping over the n
+// obstacles.  The trajectory's values at t are loaded once for n outputs,
+// consecutive lanes touch consecutive t of a row of alpha or d, and a thread
+// keeps several independent row accesses in flight.
+constexpr int kItemThreads = 512;
+inline int item_threads(int items) { return std::min(kItemThreads, (items + 63) / 64 * 64); }
+
+// ---- xi3/xi4: alpha_ij, d_ij for every (l, i, j, t); items m q .. (m + 1) q - 1
+// are the velocity/acceleration pairs alpha_v, d_v, alpha_a, d_a at t = k - m q.
+// The items of all trajectories form one flat range over small blocks, so
+// the last blocks of a launch are short.
+// rows per chunk of loads (half for FP64, whose values take two registers)
+template <typename T> constexpr int kProjChunk = sizeof(T) == 4 ? 8 : 4;
 
 template <typename T>
-__global__ void k_project(Desc D, Ptrs<T> w) {
-  const int lane = threadIdx.x & 63;
-  const int row = int(blockIdx.x) * kRowsPerBlock + int(threadIdx.x) / 64;
-  const int q = D.q, m = D.m, n = D.n, mn = m * n, B = D.B;
+__global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
+  __shared__ T ell[4][AM_MAX_OBS];  // a_j, b_j (grown by the circle radius), 1/a_j^2, 1/b_j^2
+  const int q = D.q, m = D.m, n = D.n;
+  const int per = (m + 1) * q;
+  const int g = int(blockIdx.x) * kThreads + int(threadIdx.x);
   const bool slack = D.flags & AM_XTILDE_SLACK, literal = D.flags & AM_ALPHA_LITERAL;
-  if (row < B * mn) {
-    const int l = row / mn, ij = row - l * mn, i = ij / n, j = ij - i * n;
-    const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
-    const T ri = T(D.r[i]);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
     const T a = static_cast<const T *>(D.oa)[j] + T(D.rc), b = static_cast<const T *>(D.ob)[j] + T(D.rc);
-    const T *gox = static_cast<const T *>(D.ox) + size_t(j) * q, *goy = static_cast<const T *>(D.oy) + size_t(j) * q;
-    T *oal = w.alpha + size_t(row) * q, *od = w.d + size_t(row) * q;
-    for (int t = lane; t < q; t += 64) {
+    ell[0][j] = a;
+    ell[1][j] = b;
+    ell[2][j] = T(1) / (a * a);
+    ell[3][j] = T(1) / (b * b);
+  }
+  __syncthreads();
+  if (g >= D.B * per) return;
+  const int l = g / per, k = g - l * per;
+  const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
+  const T *ox = static_cast<const T *>(D.ox), *oy = static_cast<const T *>(D.oy);
+  const T offx = T(D.offx), offy = T(D.offy);
+  {
+    const int i = k / q, t = k - i * q;
+    if (i < m) {
+      const T ri = T(D.r[i]);
       const T ux = slack ? tr[3 * q + t] : p3[q + t], uy = slack ? tr[7 * q + t] : p3[2 * q + t];
-      const T xt = tr[t] + ri * ux - (gox[t] - T(D.offx));
-      const T yt = tr[4 * q + t] + ri * uy - (goy[t] - T(D.offy));
-      T al, dd;
-      if (!literal) {
-        // elliptic angle: the point (a d cos al, b d sin al) is (xt, yt)
-        // itself, so d = sqrt(xt^2/a^2 + yt^2/b^2) (eq. compute_zeta_3)
-        al = atan2z(a * yt, b * xt);
-        dd = fmax(T(1), Num<T>::sqrt_(xt * xt / (a * a) + yt * yt / (b * b)));
-      } else {
-        al = atan2z(yt, xt);
-        T sa, ca;
-        Num<T>::sincos_(al, &sa, &ca);
-        dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
+      const T px = tr[t] + ri * ux, py = tr[4 * q + t] + ri * uy;
+      const size_t row0 = (size_t(l) * m + i) * n;
+      T *oal = w.alpha + row0 * q + t, *od = w.d + row0 * q + t;
+      const T *oxt = ox + t, *oyt = oy + t;
+      // obstacle positions are loaded a chunk at a time, so one memory
+      // latency covers a chunk of outputs
+      for (int j0 = 0; j0 < n; j0 += kProjChunk<T>) {
+        T gx[kProjChunk<T>], gy[kProjChunk<T>];
+#pragma unroll
+        for (int u = 0; u < kProjChunk<T>; ++u) {
+          const int j = j0 + u < n ? j0 + u : n - 1;
+          gx[u] = oxt[j * q];
+          gy[u] = oyt[j * q];
+        }
+#pragma unroll
+        for (int u = 0; u < kProjChunk<T>; ++u) {
+          const int j = j0 + u;
+          if (j >= n) break;
+          const T a = ell[0][j], b = ell[1][j];
+          const T xt = px - (gx[u] - offx), yt = py - (gy[u] - offy);
+          T al, dd;
+          if (!literal) {
+            // elliptic angle: the point (a d cos al, b d sin al) is (xt, yt)
+            // itself, so d = sqrt(xt^2/a^2 + yt^2/b^2) (eq. compute_zeta_3)
+            al = atan2z(a * yt, b * xt);
+            dd = fmax(T(1), Num<T>::sqrt_fast(xt * xt * ell[2][j] + yt * yt * ell[3][j]));
+          } else {
+            al = atan2z(yt, xt);
+            T sa, ca;
+            Num<T>::sincos_(al, &sa, &ca);
+            dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
+          }
+          oal[size_t(j) * q] = al;
+          od[size_t(j) * q] = dd;
+        }
       }
-      oal[t] = al;
-      od[t] = dd;
-    }
-  } else if (row < B * mn + B) {
-    const int l = row - B * mn;
-    const T *tr = w.traj8 + size_t(l) * 8 * q;
-    T *o = w.va4 + size_t(l) * 4 * q;
-    for (int t = lane; t < q; t += 64) {
+    } else {
       const T xd = tr[q + t], yd = tr[5 * q + t], xdd = tr[2 * q + t], ydd = tr[6 * q + t];
       const T av = atan2z(yd, xd), aa = atan2z(ydd, xdd);
       T sv, cv, sa, ca;
       Num<T>::sincos_(av, &sv, &cv);
       Num<T>::sincos_(aa, &sa, &ca);
+      T *o = w.va4 + size_t(l) * 4 * q;
       o[t] = av;
       o[q + t] = fmin(T(1), fmax(T(0), (xd * cv + yd * sv) / T(D.vmax)));
       o[2 * q + t] = aa;
@@ -247,65 +281,110 @@ __global__ void k_project(Desc D, Ptrs<T> w) {
   }
 }
 
-// ---- residual channels of F xi - g per (l, t), reading alpha and d
+// ---- residual channels of F xi - g per (l, t), reading alpha and d.  Item
+// (i, t) sums circle i's deviations over the obstacles; the m partial sums
+// of a t meet in LDS and one thread per t forms the channels.
+template <typename T> constexpr int kTgtChunk = sizeof(T) == 4 ? 8 : 4;  // d_ij loads issued together
+
 template <typename T>
-__global__ void k_targets(Desc D, Ptrs<T> w) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= D.B * D.q) return;
-  const int l = g / D.q, t = g % D.q, q = D.q, m = D.m, n = D.n;
+__global__ __launch_bounds__(kItemThreads) void k_targets(Desc D, Ptrs<T> w) {
+  __shared__ T part[2][AM_MAX_CIRCLES * AM_MAX_Q];
+  __shared__ T ell[2][AM_MAX_OBS];
+  const int l = blockIdx.x;
+  const int q = D.q, m = D.m, n = D.n;
   const bool slack = D.flags & AM_XTILDE_SLACK, literal = D.flags & AM_ALPHA_LITERAL;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    ell[0][j] = static_cast<const T *>(D.oa)[j] + T(D.rc);
+    ell[1][j] = static_cast<const T *>(D.ob)[j] + T(D.rc);
+  }
+  __syncthreads();
   const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
-  const T x = tr[t], c = tr[3 * q + t], y = tr[4 * q + t], s = tr[7 * q + t];
-  const T cp = p3[q + t], sp = p3[2 * q + t];
-  const T ux = slack ? c : cp, uy = slack ? s : sp;
-  T Dx = 0, Dy = 0, DRx = 0, DRy = 0;
-  const T *al = w.alpha + size_t(l) * m * n * q, *dd = w.d + size_t(l) * m * n * q;
-  for (int i = 0; i < m; ++i) {
+  const T *va = w.va4 + size_t(l) * 4 * q;
+  const T *ox = static_cast<const T *>(D.ox), *oy = static_cast<const T *>(D.oy);
+  for (int k = threadIdx.x; k < m * q; k += blockDim.x) {
+    const int i = k / q, t = k - i * q;
+    const T x = tr[t], c = tr[3 * q + t], y = tr[4 * q + t], s = tr[7 * q + t];
+    const T ux = slack ? c : p3[q + t], uy = slack ? s : p3[2 * q + t];
     const T ri = T(D.r[i]);
+    const size_t base = (size_t(l) * m + i) * n * q + t;
+    const T *al = w.alpha + base, *dd = w.d + base;
+    // circle i: sum over obstacles of the deviation of the target from the
+    // circle centre.  Under the elliptic angle a point with d > 1 lies
+    // outside the ellipse and is its own target (eqs. zeta_2,
+    // compute_zeta_3), so the deviation is exactly zero; the literal angle
+    // has no such fixed points.
     T sx = 0, sy = 0;
-#pragma unroll 4
-    for (int j = 0; j < n; ++j) {
-      const size_t e = size_t(i * n + j) * q + t;
-      const T a = static_cast<const T *>(D.oa)[j] + T(D.rc), b = static_cast<const T *>(D.ob)[j] + T(D.rc);
-      const T oxj = static_cast<const T *>(D.ox)[j * q + t] - T(D.offx);
-      const T oyj = static_cast<const T *>(D.oy)[j * q + t] - T(D.offy);
-      // deviation of the target g from the current circle centre.  Under
-      // the elliptic angle a point with d > 1 lies outside the ellipse and
-      // is its own target (eqs. zeta_2, compute_zeta_3), so the deviation is
-      // exactly zero; the literal angle has no such fixed points.
-      if (literal || dd[e] <= T(1)) {
-        T sa, ca;
-        Num<T>::sincos_(al[e], &sa, &ca);
-        sx += a * dd[e] * ca - (x + ri * ux - oxj);
-        sy += b * dd[e] * sa - (y + ri * uy - oyj);
+    const T *oxt = ox + t, *oyt = oy + t;
+    // a chunk of d_ij in one memory latency; colliding rows (d_ij <= 1, a
+    // few percent) then load their angle and obstacle position
+    for (int j0 = 0; j0 < n; j0 += kTgtChunk<T>) {
+      T dv[kTgtChunk<T>];
+#pragma unroll
+      for (int u = 0; u < kTgtChunk<T>; ++u) dv[u] = j0 + u < n ? dd[size_t(j0 + u) * q] : T(2);
+#pragma unroll
+      for (int u = 0; u < kTgtChunk<T>; ++u) {
+        const int j = j0 + u;
+        if (j < n && (literal || dv[u] <= T(1))) {
+          const T oxj = oxt[j * q] - T(D.offx), oyj = oyt[j * q] - T(D.offy);
+          T sa, ca;
+          Num<T>::sincos_(al[size_t(j) * q], &sa, &ca);
+          sx += ell[0][j] * dv[u] * ca - (x + ri * ux - oxj);
+          sy += ell[1][j] * dv[u] * sa - (y + ri * uy - oyj);
+        }
       }
     }
-    Dx += sx; Dy += sy; DRx += ri * sx; DRy += ri * sy;
+    part[0][k] = sx;
+    part[1][k] = sy;
   }
-  T s1 = 0, s2 = 0;
-  for (int i = 0; i < m; ++i) { s1 += T(D.r[i]); s2 += T(D.r[i]) * T(D.r[i]); }
-  s1 *= T(n);
-  s2 *= T(n);
-  const T *va = w.va4 + size_t(l) * 4 * q;
-  T sv, cv, sa, ca;
-  Num<T>::sincos_(va[t], &sv, &cv);
-  Num<T>::sincos_(va[2 * q + t], &sa, &ca);
-  const T vm = T(D.vmax), am = T(D.amax);
-  const T dc = c - cp, ds = s - sp;
-  const T k1 = slack ? T(0) : s1, k2 = (slack ? T(0) : s2) + T(1);
-  T *ch = w.chan + size_t(l) * 9 * q + t;
-  // inside the disc (d_v < 1) the velocity is its own target
-  const bool vin = va[q + t] < T(1), ain = va[3 * q + t] < T(1);
-  ch[0] = vin ? T(0) : tr[q + t] - vm * va[q + t] * cv;          // xdot - g_v
-  ch[q] = ain ? T(0) : tr[2 * q + t] - am * va[3 * q + t] * ca;  // xddot - g_a
-  ch[2 * q] = k1 * dc - Dx;                         // sum_ij (x + r_i c - g_ob)
-  ch[3 * q] = k2 * dc - DRx;                        // sum_ij r_i (...) + (c - cos psi)
-  ch[4 * q] = vin ? T(0) : tr[5 * q + t] - vm * va[q + t] * sv;
-  ch[5 * q] = ain ? T(0) : tr[6 * q + t] - am * va[3 * q + t] * sa;
-  ch[6 * q] = k1 * ds - Dy;
-  ch[7 * q] = k2 * ds - DRy;
-  const T psi_sign = (D.flags & AM_LAMPSI_LITERAL) ? T(-1) : T(1);
-  ch[8 * q] = psi_sign * (p3[t] - w.psih[size_t(l) * q + t]);
+  // inputs of the channels at t = threadIdx.x, loaded before the barrier so
+  // that their latency overlaps the wait (q <= blockDim.x whenever m q fits
+  // one block; otherwise the channel loop below loads them itself)
+  T pre[14];
+  const int t0 = threadIdx.x;
+  if (t0 < q) {
+    pre[0] = tr[q + t0]; pre[1] = tr[2 * q + t0]; pre[2] = tr[3 * q + t0]; pre[3] = tr[5 * q + t0];
+    pre[4] = tr[6 * q + t0]; pre[5] = tr[7 * q + t0]; pre[6] = p3[t0]; pre[7] = p3[q + t0];
+    pre[8] = p3[2 * q + t0]; pre[9] = w.psih[size_t(l) * q + t0];
+    pre[10] = va[t0]; pre[11] = va[2 * q + t0]; pre[12] = va[q + t0]; pre[13] = va[3 * q + t0];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < q; t += blockDim.x) {
+    if (t != t0) {
+      pre[0] = tr[q + t]; pre[1] = tr[2 * q + t]; pre[2] = tr[3 * q + t]; pre[3] = tr[5 * q + t];
+      pre[4] = tr[6 * q + t]; pre[5] = tr[7 * q + t]; pre[6] = p3[t]; pre[7] = p3[q + t];
+      pre[8] = p3[2 * q + t]; pre[9] = w.psih[size_t(l) * q + t];
+      pre[10] = va[t]; pre[11] = va[2 * q + t]; pre[12] = va[q + t]; pre[13] = va[3 * q + t];
+    }
+    const T c = pre[2], s = pre[5];
+    const T cp = pre[7], sp = pre[8];
+    T Dx = 0, Dy = 0, DRx = 0, DRy = 0, s1 = 0, s2 = 0;
+    for (int i = 0; i < m; ++i) {
+      const T ri = T(D.r[i]), px = part[0][i * q + t], py = part[1][i * q + t];
+      Dx += px; Dy += py; DRx += ri * px; DRy += ri * py;
+      s1 += ri; s2 += ri * ri;
+    }
+    s1 *= T(n);
+    s2 *= T(n);
+    T sv, cv, sa, ca;
+    Num<T>::sincos_(pre[10], &sv, &cv);
+    Num<T>::sincos_(pre[11], &sa, &ca);
+    const T vm = T(D.vmax), am = T(D.amax);
+    const T dc = c - cp, ds = s - sp;
+    const T k1 = slack ? T(0) : s1, k2 = (slack ? T(0) : s2) + T(1);
+    T *ch = w.chan + size_t(l) * 9 * q + t;
+    // inside the disc (d_v < 1) the velocity is its own target
+    const bool vin = pre[12] < T(1), ain = pre[13] < T(1);
+    ch[0] = vin ? T(0) : pre[0] - vm * pre[12] * cv;  // xdot - g_v
+    ch[q] = ain ? T(0) : pre[1] - am * pre[13] * ca;  // xddot - g_a
+    ch[2 * q] = k1 * dc - Dx;                         // sum_ij (x + r_i c - g_ob)
+    ch[3 * q] = k2 * dc - DRx;                        // sum_ij r_i (...) + (c - cos psi)
+    ch[4 * q] = vin ? T(0) : pre[3] - vm * pre[12] * sv;
+    ch[5 * q] = ain ? T(0) : pre[4] - am * pre[13] * sa;
+    ch[6 * q] = k1 * ds - Dy;
+    ch[7 * q] = k2 * ds - DRy;
+    const T psi_sign = (D.flags & AM_LAMPSI_LITERAL) ? T(-1) : T(1);
+    ch[8 * q] = psi_sign * (pre[6] - pre[9]);
+  }
 }
 
 // ---- F^T (F xi - g), multipliers and the next right-hand side (one wave
@@ -568,21 +647,20 @@ hipError_t run(const Desc &D, void *ws, hipStream_t st) {
   const PlainWs L = plain_layout(D.B, D.q, NV, D.m, D.n);
   const Ptrs<T> w = ptrs_of<T>(ws, L);
   const int B = D.B, q = D.q;
-  const int proj_blocks = int((size_t(B) * D.m * D.n + B + kRowsPerBlock - 1) / kRowsPerBlock);
   const int wave_blocks = (B + 3) / 4;
   hipLaunchKernelGGL((k_enter<T, NV>), dim3(blocks_for(size_t(B) * 5 * NV)), dim3(kThreads), 0, st, D, w);
   // step 1: initial xi3, xi4 from the given trajectories
   hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
   hipLaunchKernelGGL((k_eval_psi<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
-  hipLaunchKernelGGL((k_project<T>), dim3(proj_blocks), dim3(kThreads), 0, st, D, w);
-  hipLaunchKernelGGL((k_targets<T>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
+  hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(size_t(B) * (D.m + 1) * q)), dim3(kThreads), 0, st, D, w);
+  hipLaunchKernelGGL((k_targets<T>), dim3(B), dim3(item_threads(D.m * q)), 0, st, D, w);
   contract<T, NV>(D, w, st, 0);
   for (int it = 0; it < D.K; ++it) {
     xi1<T, NV>(D, w, st);
     hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_xi2<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w);
-    hipLaunchKernelGGL((k_project<T>), dim3(proj_blocks), dim3(kThreads), 0, st, D, w);
-    hipLaunchKernelGGL((k_targets<T>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
+    hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(size_t(B) * (D.m + 1) * q)), dim3(kThreads), 0, st, D, w);
+    hipLaunchKernelGGL((k_targets<T>), dim3(B), dim3(item_threads(D.m * q)), 0, st, D, w);
     contract<T, NV>(D, w, st, 1);
   }
   const size_t exit_work = std::max(size_t(B) * 5 * NV, size_t(B) * q);
