@@ -65,6 +65,10 @@ __device__ __forceinline__ void sincos_f32(float a, float *s, float *c) {
 template <>
 struct Num<float> {
   static __device__ __forceinline__ float rsqrt(float x) { return rsqrtf(x); }
+  // hardware reciprocal square root (about 1 ulp) without the rescaling of
+  // subnormal arguments: a zero or subnormal argument may give +inf, which
+  // callers must tolerate
+  static __device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
   static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
   // hardware square root (about 1 ulp), for bounds that tolerate it
   static __device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -78,6 +82,7 @@ struct Num<float> {
 template <>
 struct Num<double> {
   static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+  static __device__ __forceinline__ double rsqrt_fast(double x) { return 1.0 / ::sqrt(x); }
   static __device__ __forceinline__ double sqrt_(double x) { return ::sqrt(x); }
   static __device__ __forceinline__ double sqrt_fast(double x) { return ::sqrt(x); }
   static __device__ __forceinline__ double atan2_(double y, double x) { return ::atan2(y, x); }

@@ -81,6 +81,10 @@ __device__ __forceinline__ double lane_xor1(double v) {
 // of any addition.
 template <typename T, int G, int ROWS>
 __device__ __forceinline__ T wave_sum_many(const T (&p)[G], T *red, int lane) {
+  // A plain add takes the neighbour through its DPP operand (one
+  // instruction); fused into the caller's product it would need a separate
+  // DPP move and the product twice.
+#pragma clang fp contract(off)
   static_assert(ROWS <= kRedRows && ROWS % 2 == 0, "rows per pass");
   const int odd = lane & 1, col = lane >> 1;
   T s = T(0);
@@ -274,7 +278,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   auto exchange_sum = [&](int slot) -> T { return xch[slot] + xch[kXchHalf + slot]; };
 
   // Projection of one obstacle's rows at this lane's t for every circle
-  // (fast form; a non-finite sum is redone element by element afterwards).
+  // (fast form; a non-finite sum, as from a zero or subnormal r2, is redone
+  // element by element afterwards).
   // p = (a^2, b^2, ab, max(a, b)) of the inflated ellipse.
   T Sx[kMaxC], Sy[kMaxC];
   auto project_obstacle = [&](T ux, T uy, const Pair<T> o, const Quad<T> p) {
@@ -284,7 +289,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       if (i < m) {
         const T xt = dxj + rr[i] * ux, yt = dyj + rr[i] * uy;
         const T r2 = p.b * xt * xt + p.a * yt * yt;   // b^2 x~^2 + a^2 y~^2
-        const T f1 = fmax(T(0), p.c * Num<T>::rsqrt(r2) - T(1));
+        const T f1 = fmax(T(0), p.c * Num<T>::rsqrt_fast(r2) - T(1));
         Sx[i] += xt * f1;
         Sy[i] += yt * f1;
       }
@@ -382,44 +387,53 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
         }
       }
     }
-    // Exact zero (or underflowed) offsets make the fast form non-finite;
-    // redo those sums element by element (alpha := 0 at the zero vector).
-#pragma unroll
-    for (int i = 0; i < kMaxC; ++i) {
-      if (i < m && !(isfinite(Sx[i]) && isfinite(Sy[i]))) {
-        T sx = T(0), sy = T(0);
-        for (int j = 0; j < n; ++j) {
-          const Pair<T> o = oxy[j * q + tt];
-          const T xt = x + rr[i] * ux - o.x, yt = y + rr[i] * uy - o.y;
-          const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
-          if (xt == T(0) && yt == T(0)) {
-            sx += a;   // alpha = 0, d = 1: target (x_j + a, y_j)
-          } else if (!literal_alpha) {
-            const T rr_ = Num<T>::hypot_(b * xt, a * yt);
-            const T f1 = fmax(T(0), (a * b) / rr_ - T(1));
-            sx += xt * f1;
-            sy += yt * f1;
-          } else {
-            const T rho0 = Num<T>::hypot_(xt, yt);
-            const T ca = xt / rho0, sa = yt / rho0;
-            const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
-            sx += a * dd * ca - xt;
-            sy += b * dd * sa - yt;
-          }
-        }
-        Sx[i] = sx;
-        Sy[i] = sy;
-      }
-    }
     T Dx = 0, Dy = 0, DRx = 0, DRy = 0;
+    auto sum_circles = [&]() {
+      Dx = Dy = DRx = DRy = T(0);
 #pragma unroll
-    for (int i = 0; i < kMaxC; ++i) {
-      Dx += Sx[i]; Dy += Sy[i];
-      DRx += rr[i] * Sx[i]; DRy += rr[i] * Sy[i];
+      for (int i = 0; i < kMaxC; ++i) {
+        Dx += Sx[i]; Dy += Sy[i];
+        DRx += rr[i] * Sx[i]; DRy += rr[i] * Sy[i];
+      }
+    };
+    sum_circles();
+    // Exact zero (or underflowed) offsets make the fast form non-finite, and
+    // a non-finite term of any circle makes Dx or Dy non-finite: then redo
+    // those circles' sums element by element (alpha := 0 at the zero vector).
+    if (__ballot(!(isfinite(Dx) && isfinite(Dy))) != 0) {
+#pragma unroll
+      for (int i = 0; i < kMaxC; ++i) {
+        if (i < m && !(isfinite(Sx[i]) && isfinite(Sy[i]))) {
+          T sx = T(0), sy = T(0);
+          for (int j = 0; j < n; ++j) {
+            const Pair<T> o = oxy[j * q + tt];
+            const T xt = x + rr[i] * ux - o.x, yt = y + rr[i] * uy - o.y;
+            const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
+            if (xt == T(0) && yt == T(0)) {
+              sx += a;   // alpha = 0, d = 1: target (x_j + a, y_j)
+            } else if (!literal_alpha) {
+              const T rr_ = Num<T>::hypot_(b * xt, a * yt);
+              const T f1 = fmax(T(0), (a * b) / rr_ - T(1));
+              sx += xt * f1;
+              sy += yt * f1;
+            } else {
+              const T rho0 = Num<T>::hypot_(xt, yt);
+              const T ca = xt / rho0, sa = yt / rho0;
+              const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
+              sx += a * dd * ca - xt;
+              sy += b * dd * sa - yt;
+            }
+          }
+          Sx[i] = sx;
+          Sy[i] = sy;
+        }
+      }
+      sum_circles();
     }
     // velocity / acceleration: part of (xdot, ydot) outside the disc
-    const T fv = fmax(T(0), T(1) - vmax * Num<T>::rsqrt(xd * xd + yd * yd));
-    const T fa = fmax(T(0), T(1) - amax * Num<T>::rsqrt(xdd * xdd + ydd * ydd));
+    // (a zero or subnormal speed gives 1/sqrt = +inf and a factor of 0)
+    const T fv = fmax(T(0), T(1) - vmax * Num<T>::rsqrt_fast(xd * xd + yd * yd));
+    const T fa = fmax(T(0), T(1) - amax * Num<T>::rsqrt_fast(xdd * xdd + ydd * ydd));
     const T rvx = xd * fv, rvy = yd * fv, rax = xdd * fa, ray = ydd * fa;
     const T dc = cc - cps, ds = ss - sps;
     const T k1 = slack ? T(0) : s1, k2 = (slack ? T(0) : s2) + T(1);
