@@ -136,6 +136,39 @@ __device__ __forceinline__ T row_dot(const T *op, int I, const T *v) {
   return acc0 + acc1;
 }
 
+// Row I of a [2nv][2nv] operator in the Quad layout of row_dot, copied to
+// registers (zero past 2nv).
+template <typename T, int NV>
+__device__ __forceinline__ void row_load(const T *op, int I, T (&r)[pad4(2 * NV)]) {
+  constexpr int N2 = 2 * NV, C = pad4(N2) / 4;
+  const Quad<T> *o = reinterpret_cast<const Quad<T> *>(op);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const Quad<T> a = o[c * N2 + I];
+    r[4 * c] = a.a;
+    r[4 * c + 1] = a.b;
+    r[4 * c + 2] = 4 * c + 2 < N2 ? a.c : T(0);
+    r[4 * c + 3] = 4 * c + 3 < N2 ? a.d : T(0);
+  }
+}
+
+// The same product with the row in registers.
+template <typename T, int NV>
+__device__ __forceinline__ T row_dot_reg(const T (&r)[pad4(2 * NV)], const T *v) {
+  constexpr int N2 = 2 * NV, C = pad4(N2) / 4;
+  const Quad<T> *vv = reinterpret_cast<const Quad<T> *>(v);
+  T acc0 = T(0), acc1 = T(0);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const Quad<T> b = vv[c];
+    acc0 += r[4 * c] * b.a;
+    acc1 += r[4 * c + 1] * b.b;
+    if (4 * c + 2 < N2) acc0 += r[4 * c + 2] * b.c;
+    if (4 * c + 3 < N2) acc1 += r[4 * c + 3] * b.d;
+  }
+  return acc0 + acc1;
+}
+
 template <typename T, int NV, int RED>
 __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds, const FusedLds &L,
                            int lane, int wave) {
@@ -477,18 +510,34 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   eval_xy();
   eval_psi();
   psih = psi;
-  T gz = prow ? row_dot<T, NV>(GF, I, vz + axis * A2) : T(0);   // row of F^T F z
+  // rows I of KKT^-1 (position block) and of F^T F: in registers for FP32
+  // under the two-wavefront register budget, else read from LDS
+  constexpr bool kRowsInRegs = RED == kRedRows && sizeof(T) == 4;
+  T m1row[A2], gfrow[A2];
+  if constexpr (kRowsInRegs) {
+    row_load<T, NV>(M1, I, m1row);
+    row_load<T, NV>(GF, I, gfrow);
+  }
+  auto m1_dot = [&](const T *v) {
+    if constexpr (kRowsInRegs) return row_dot_reg<T, NV>(m1row, v);
+    else return row_dot<T, NV>(M1, I, v);
+  };
+  auto gf_dot = [&](const T *v) {
+    if constexpr (kRowsInRegs) return row_dot_reg<T, NV>(gfrow, v);
+    else return row_dot<T, NV>(GF, I, v);
+  };
+  T gz = prow ? gf_dot(vz + axis * A2) : T(0);   // row of F^T F z
   project_reduce(false);
   if (prow) vrhs[axis * A2 + I] = lam + rho * (gz - tr);
   wave_sync();
 
   for (int it = 0; it < K; ++it) {
     // ---- xi1: [z; mu] = KKT^-1 [lambda + rho F^T g; b]  (eqs. over_3, zeta_1_sepration_3)
-    if (prow) vz[axis * A2 + I] = hreg + row_dot<T, NV>(M1, I, vrhs + axis * A2);
+    if (prow) vz[axis * A2 + I] = hreg + m1_dot(vrhs + axis * A2);
     wave_sync();
     eval_xy();
     // F^T F z of the new z, used by the next right-hand side
-    gz = prow ? row_dot<T, NV>(GF, I, vz + axis * A2) : T(0);
+    gz = prow ? gf_dot(vz + axis * A2) : T(0);
 
     // ---- xi2: psi_hat = atan2(s, c) on the branch nearest psi^k, then the
     // heading QP (eq. compute_convex_surrogate):
