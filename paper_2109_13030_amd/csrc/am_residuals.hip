@@ -1,10 +1,12 @@
 // am_residuals.hip -- per-trajectory residual statistics of the current state
-// (one wavefront per trajectory), plus the small kernel that fills the
+// (two wavefronts per trajectory), plus the small kernel that fills the
 // problem table of multi-problem launches.
 //
 // The angles and distances are recomputed by the closed forms of eqs.
 // (zeta_2, alpha_v, alpha_a, compute_zeta_3, compute_dv, compute_da) from the
-// current trajectories, which is exactly what the last xi3/xi4 step produced.
+// current trajectories, which is exactly what the last xi3/xi4 step produced;
+// under the elliptic angle and for the velocity/acceleration discs the
+// residual follows from those forms without evaluating the angle.
 #include <hip/hip_runtime.h>
 
 #include "am_device.h"
@@ -38,27 +40,46 @@ struct ResArgs {
   void *out;
 };
 
+constexpr int kTrajPerResBlock = kWavesPerBlock / 2;
+constexpr int kResChunk = 4;    // obstacle positions loaded together
+constexpr int kResStats = 10;   // per-wave statistics combined across the pair
+
 template <typename T, int NV>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void residual_kernel(ResArgs A) {
+  // per-obstacle constants of the inflated ellipses: a, b, ab, 1/a^2, 1/b^2
+  __shared__ T ell[5][AM_MAX_OBS];
   const Desc &D = A.d;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int l = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (l >= D.B) return;
   const int q = D.q, m = D.m, n = D.n;
+  const T rc = T(D.rc);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const T a = static_cast<const T *>(D.oa)[j] + rc, b = static_cast<const T *>(D.ob)[j] + rc;
+    ell[0][j] = a;
+    ell[1][j] = b;
+    ell[2][j] = a * b;
+    ell[3][j] = T(1) / (a * a);
+    ell[4][j] = T(1) / (b * b);
+  }
+  __syncthreads();
+  // two wavefronts per trajectory, taking alternate time steps
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int half = wave & 1, slot = wave >> 1;
+  const int l = blockIdx.x * kTrajPerResBlock + slot;
+  const bool live = l < D.B;
   const bool slack = D.flags & AM_XTILDE_SLACK, literal = D.flags & AM_ALPHA_LITERAL;
   const T *P = static_cast<const T *>(A.P), *Pd = static_cast<const T *>(A.Pd),
           *Pdd = static_cast<const T *>(A.Pdd);
-  const T *cx = static_cast<const T *>(D.cx) + size_t(l) * NV, *cc = static_cast<const T *>(D.cc) + size_t(l) * NV;
-  const T *cy = static_cast<const T *>(D.cy) + size_t(l) * NV, *cs = static_cast<const T *>(D.cs) + size_t(l) * NV;
-  const T *cp = static_cast<const T *>(D.cpsi) + size_t(l) * NV;
+  const int lc = live ? l : 0;
+  const T *cx = static_cast<const T *>(D.cx) + size_t(lc) * NV, *cc = static_cast<const T *>(D.cc) + size_t(lc) * NV;
+  const T *cy = static_cast<const T *>(D.cy) + size_t(lc) * NV, *cs = static_cast<const T *>(D.cs) + size_t(lc) * NV;
+  const T *cp = static_cast<const T *>(D.cpsi) + size_t(lc) * NV;
   const T *gox = static_cast<const T *>(D.ox), *goy = static_cast<const T *>(D.oy);
-  const T *goa = static_cast<const T *>(D.oa), *gob = static_cast<const T *>(D.ob);
-  const T vmax = T(D.vmax), amax = T(D.amax), rc = T(D.rc);
+  const T vmax = T(D.vmax), amax = T(D.amax);
   const T pi = T(3.14159265358979323846);
 
-  T fcmax = 0, fcsq = 0, level = T(INFINITY), fvmax = 0, famax = 0, slk = 0, head = 0, bc = 0, cost = 0;
-  T vex = T(-INFINITY), aex = T(-INFINITY);
-  for (int t = lane; t < q; t += kWave) {
+  // squared maxima and minima are tracked, one square root at the end
+  T fc2max = 0, fcsq = 0, lvl2 = T(INFINITY), slk = 0, head = 0, bc = 0, cost = 0;
+  T v2max = 0, a2max = 0;
+  for (int t = half + 2 * lane; live && t < q; t += 2 * kWave) {
     T x = 0, xd = 0, xdd = 0, y = 0, yd = 0, ydd = 0, c = 0, s = 0, psi = 0, psidd = 0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -67,38 +88,65 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void residual_kernel(ResArgs
       y += p * cy[k]; yd += pd * cy[k]; ydd += pdd * cy[k];
       c += p * cc[k]; s += p * cs[k]; psi += p * cp[k]; psidd += pdd * cp[k];
     }
-    const T cpsi = Num<T>::cos_(psi), spsi = Num<T>::sin_(psi);
-    for (int i = 0; i < m; ++i) {
-      const T ri = T(D.r[i]);
-      for (int j = 0; j < n; ++j) {
-        const T a = goa[j] + rc, b = gob[j] + rc;
-        const T px = x + ri * cpsi - gox[j * q + t], py = y + ri * spsi - goy[j * q + t];
-        const T xt = slack ? x + ri * c - gox[j * q + t] : px;
-        const T yt = slack ? y + ri * s - goy[j * q + t] : py;
-        const T al = literal ? atan2z(yt, xt) : atan2z(a * yt, b * xt);
-        const T ca = Num<T>::cos_(al), sa = Num<T>::sin_(al);
-        const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
-        const T fx = px - a * dd * ca, fy = py - b * dd * sa;
-        const T f2 = fx * fx + fy * fy;
-        fcmax = fmax(fcmax, Num<T>::sqrt_(f2));
-        fcsq += f2;
-        level = fmin(level, Num<T>::sqrt_(px * px / (a * a) + py * py / (b * b)) - T(1));
+    T spsi, cpsi;
+    Num<T>::sincos_(psi, &spsi, &cpsi);
+    // obstacles outermost, their positions at t loaded a chunk at a time
+    for (int j0 = 0; j0 < n; j0 += kResChunk) {
+      T gx[kResChunk], gy[kResChunk];
+#pragma unroll
+      for (int u = 0; u < kResChunk; ++u) {
+        const int j = j0 + u < n ? j0 + u : n - 1;
+        gx[u] = gox[j * q + t];
+        gy[u] = goy[j * q + t];
+      }
+#pragma unroll
+      for (int u = 0; u < kResChunk; ++u) {
+        const int j = j0 + u;
+        if (j >= n) break;
+        const T a = ell[0][j], b = ell[1][j];
+        for (int i = 0; i < m; ++i) {
+          const T ri = T(D.r[i]);
+          const T px = x + ri * cpsi - gx[u], py = y + ri * spsi - gy[u];   // circle centre - obstacle
+          const T xt = slack ? x + ri * c - gx[u] : px, yt = slack ? y + ri * s - gy[u] : py;
+          T fx, fy;
+          if (!literal) {
+            // elliptic angle: (a d cos al, b d sin al) = (xt, yt) max(1, ab/r),
+            // r = |(b xt, a yt)| (eqs. zeta_2, compute_zeta_3); al = 0, d = 1
+            // at the zero vector
+            const T r2 = b * b * xt * xt + a * a * yt * yt;
+            if (r2 > T(0)) {
+              const T g = fmax(T(1), ell[2][j] * Num<T>::rsqrt(r2));
+              fx = px - xt * g;
+              fy = py - yt * g;
+            } else {
+              fx = px - a;
+              fy = py;
+            }
+          } else {
+            const T al = atan2z(yt, xt);
+            T sa, ca;
+            Num<T>::sincos_(al, &sa, &ca);
+            const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
+            fx = px - a * dd * ca;
+            fy = py - b * dd * sa;
+          }
+          const T f2 = fx * fx + fy * fy;
+          fc2max = fmax(fc2max, f2);
+          fcsq += f2;
+          lvl2 = fmin(lvl2, px * px * ell[3][j] + py * py * ell[4][j]);
+        }
       }
     }
-    const T av = atan2z(yd, xd), aa = atan2z(ydd, xdd);
-    const T dv = fmin(T(1), fmax(T(0), (xd * Num<T>::cos_(av) + yd * Num<T>::sin_(av)) / vmax));
-    const T da = fmin(T(1), fmax(T(0), (xdd * Num<T>::cos_(aa) + ydd * Num<T>::sin_(aa)) / amax));
-    const T vx = xd - vmax * dv * Num<T>::cos_(av), vy = yd - vmax * dv * Num<T>::sin_(av);
-    const T ax = xdd - amax * da * Num<T>::cos_(aa), ay = ydd - amax * da * Num<T>::sin_(aa);
-    fvmax = fmax(fvmax, Num<T>::sqrt_(vx * vx + vy * vy));
-    famax = fmax(famax, Num<T>::sqrt_(ax * ax + ay * ay));
+    // velocity and acceleration: the projection onto the disc of radius
+    // v_max leaves a residual of length max(0, |v| - v_max) (eqs. alpha_v,
+    // compute_dv; likewise for a)
+    v2max = fmax(v2max, xd * xd + yd * yd);
+    a2max = fmax(a2max, xdd * xdd + ydd * ydd);
     slk = fmax(slk, fmax(fabs(c - cpsi), fabs(s - spsi)));
     T dh = atan2z(s, c) - psi;
     dh = dh - T(2) * pi * floor((dh + pi) / (T(2) * pi));
     head = fmax(head, fabs(dh));
     cost += xdd * xdd + ydd * ydd + psidd * psidd;
-    vex = fmax(vex, Num<T>::sqrt_(xd * xd + yd * yd) - vmax);
-    aex = fmax(aex, Num<T>::sqrt_(xdd * xdd + ydd * ydd) - amax);
     if (t == 0 || t == q - 1) {
       const int o = (t == 0) ? 0 : 3;
       const T vals[9] = {x, xd, xdd, y, yd, ydd, psi, T(0), T(0)};
@@ -115,24 +163,38 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void residual_kernel(ResArgs
   }
   // non-finite state values (coefficients and multipliers)
   int bad = 0;
-  const T *lam = static_cast<const T *>(D.lam) + size_t(l) * 4 * NV;
-  const T *lp = static_cast<const T *>(D.lampsi) + size_t(l) * NV;
-  if (lane < NV)
+  const T *lam = static_cast<const T *>(D.lam) + size_t(lc) * 4 * NV;
+  const T *lp = static_cast<const T *>(D.lampsi) + size_t(lc) * NV;
+  if (live && lane < NV)
     bad = !isfinite(cx[lane]) || !isfinite(cc[lane]) || !isfinite(cy[lane]) || !isfinite(cs[lane]) ||
           !isfinite(cp[lane]) || !isfinite(lp[lane]);
-  if (lane < 4 * NV) bad |= !isfinite(lam[lane]);
-  const T fbad = wave_max(T(bad ? 1 : 0));
-  fcmax = wave_max(fcmax);
-  fcsq = wave_add(fcsq);
-  level = wave_min(level);
-  fvmax = wave_max(fvmax);
-  famax = wave_max(famax);
-  slk = wave_max(slk);
-  head = wave_max(head);
-  bc = wave_max(bc);
-  cost = wave_add(cost);
-  vex = wave_max(vex);
-  aex = wave_max(aex);
+  if (live && lane < 4 * NV) bad |= !isfinite(lam[lane]);
+  // per-wave totals, then the second wave's handed to the first through LDS
+  T st[kResStats] = {wave_max(T(bad ? 1 : 0)), wave_max(fc2max), wave_add(fcsq), wave_min(lvl2),
+                     wave_max(v2max), wave_max(a2max), wave_max(slk), wave_max(head), wave_max(bc),
+                     wave_add(cost)};
+  __shared__ T other[kTrajPerResBlock][kResStats];
+  if (half == 1 && lane == 0) {
+#pragma unroll
+    for (int k = 0; k < kResStats; ++k) other[slot][k] = st[k];
+  }
+  __syncthreads();
+  if (!live || half != 0) return;
+  {
+    const T *o = other[slot];
+    st[0] = fmax(st[0], o[0]); st[1] = fmax(st[1], o[1]); st[2] += o[2]; st[3] = fmin(st[3], o[3]);
+    st[4] = fmax(st[4], o[4]); st[5] = fmax(st[5], o[5]); st[6] = fmax(st[6], o[6]);
+    st[7] = fmax(st[7], o[7]); st[8] = fmax(st[8], o[8]); st[9] += o[9];
+  }
+  const T fbad = st[0], fcmax = Num<T>::sqrt_(st[1]);
+  fcsq = st[2];
+  const T level = Num<T>::sqrt_(st[3]) - T(1);
+  const T vex = Num<T>::sqrt_(st[4]) - vmax, aex = Num<T>::sqrt_(st[5]) - amax;
+  const T fvmax = fmax(T(0), vex), famax = fmax(T(0), aex);
+  slk = st[6];
+  head = st[7];
+  bc = st[8];
+  cost = st[9];
   if (lane == 0) {
     T *o = static_cast<T *>(A.out) + size_t(l) * AM_NRES;
     const int mnq = m * n * q;
@@ -153,7 +215,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void residual_kernel(ResArgs
 
 template <typename T, int NV>
 hipError_t res_t(const ResArgs &a, hipStream_t st) {
-  const int blocks = (a.d.B + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int blocks = (a.d.B + kTrajPerResBlock - 1) / kTrajPerResBlock;
   hipLaunchKernelGGL((residual_kernel<T, NV>), dim3(blocks), dim3(kWave * kWavesPerBlock), 0, st, a);
   return hipGetLastError();
 }
