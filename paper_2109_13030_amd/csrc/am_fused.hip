@@ -369,17 +369,17 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
           T am[kVoteChunk];
 #pragma unroll
           for (int k = 0; k < kVoteChunk; ++k) {
-            const int j = j0 + k < n ? j0 + k : n - 1;
-            o[k] = oxy[j * q + tt];
-            am[k] = op[j * 8 + OP_AMAX];
+            if (j0 + k >= n) break;   // padding of the last chunk
+            o[k] = oxy[(j0 + k) * q + tt];
+            am[k] = op[(j0 + k) * 8 + OP_AMAX];
           }
 #pragma unroll
           for (int k = 0; k < kVoteChunk; ++k) {
+            if (j0 + k >= n) break;   // padding of the last chunk
             const T dx = x - o[k].x, dy = y - o[k].y;
             const T reach = ext + am[k] + margin;
             const bool near = tv & (dx * dx + dy * dy < reach * reach);
-            const uint64_t bal = __ballot(near);
-            if (j0 + k < n && bal != 0) near_set |= uint64_t(1) << (j0 + k);
+            if (__ballot(near) != 0) near_set |= uint64_t(1) << (j0 + k);
           }
         }
       }
