@@ -197,7 +197,10 @@ def run_serving(rates, n_requests, modes=("continuous", "plain"), n_clients: int
            "iterations": K, "budget_bytes": budget, "modes": {}}
 
     def one(mode, rate, count, rseed):
-        srv = am.Server(budget, streams=4, max_per_launch=64, mode=mode_ids[mode])
+        # the scheduler polls for 20 ms after its last activity (longer than
+        # the mean gap between arrivals at 50-200 Hz), so arrivals do not
+        # wait for a thread wake-up
+        srv = am.Server(budget, streams=4, max_per_launch=64, mode=mode_ids[mode], idle_spin_us=20000)
         rng = np.random.default_rng(rseed)
         steps = [0] * len(clients)
         # every robot's first (cold) request is served before the timed run;

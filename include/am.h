@@ -275,6 +275,11 @@ typedef struct {
                                    and the best one (am_select_best rule), read back
                                    with am_server_best; 0: off                          */
   double fc_tol;                /* collision tolerance of that rule [m], >= 0          */
+  int32_t idle_spin_us;         /* 0..1000000: after its last launch or submission the
+                                   scheduler keeps polling for this long before it
+                                   sleeps (a woken thread adds the OS wake-up time
+                                   to the next request's latency; spinning holds
+                                   one host core); 0: sleep at once                     */
 } am_server_config;
 
 /* One solve request.  Host arrays are copied during am_server_submit. */

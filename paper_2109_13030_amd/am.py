@@ -62,7 +62,7 @@ class State(ct.Structure):
 class ServerConfig(ct.Structure):
     _fields_ = [("hbm_budget", ct.c_size_t), ("streams", ct.c_int32), ("max_per_launch", ct.c_int32),
                 ("mode", ct.c_int32), ("dtype", ct.c_int32), ("select_best", ct.c_int32),
-                ("fc_tol", ct.c_double)]
+                ("fc_tol", ct.c_double), ("idle_spin_us", ct.c_int32)]
 
 
 class Request(ct.Structure):
@@ -366,11 +366,12 @@ class Server:
 
     def __init__(self, hbm_budget: int, streams: int = 4, max_per_launch: int = 64,
                  mode: int = SERVE_CONTINUOUS, dtype: str = "f32", select_best: bool = False,
-                 fc_tol: float = 0.05):
+                 fc_tol: float = 0.05, idle_spin_us: int = 0):
         c = ServerConfig()
         c.hbm_budget, c.streams, c.max_per_launch = int(hbm_budget), int(streams), int(max_per_launch)
         c.mode, c.dtype = int(mode), AM_F64 if dtype == "f64" else AM_F32
         c.select_best, c.fc_tol = int(bool(select_best)), float(fc_tol)
+        c.idle_spin_us = int(idle_spin_us)
         self.dtype = dtype
         s = ct.c_void_p()
         check(lib().am_server_create(ct.byref(c), ct.byref(s)))

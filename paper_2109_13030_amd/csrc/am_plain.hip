@@ -286,7 +286,17 @@ __global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
 // of a t meet in LDS and one thread per t forms the channels.
 template <typename T> constexpr int kTgtChunk = sizeof(T) == 4 ? 8 : 4;  // d_ij loads issued together
 
-template <typename T>
+// V consecutive values of a row as one aligned load
+template <typename T, int V>
+struct alignas(V * sizeof(T)) Vec {
+  T v[V];
+};
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> ldv(const T *p) {
+  return *reinterpret_cast<const Vec<T, V> *>(p);
+}
+
+template <typename T, int V>
 __global__ __launch_bounds__(kItemThreads) void k_targets(Desc D, Ptrs<T> w) {
   __shared__ T part[2][AM_MAX_CIRCLES * AM_MAX_Q];
   __shared__ T ell[2][AM_MAX_OBS];
@@ -301,10 +311,14 @@ __global__ __launch_bounds__(kItemThreads) void k_targets(Desc D, Ptrs<T> w) {
   const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
   const T *va = w.va4 + size_t(l) * 4 * q;
   const T *ox = static_cast<const T *>(D.ox), *oy = static_cast<const T *>(D.oy);
-  for (int k = threadIdx.x; k < m * q; k += blockDim.x) {
-    const int i = k / q, t = k - i * q;
-    const T x = tr[t], c = tr[3 * q + t], y = tr[4 * q + t], s = tr[7 * q + t];
-    const T ux = slack ? c : p3[q + t], uy = slack ? s : p3[2 * q + t];
+  // V consecutive time steps per item (V = 2 when q is even: every row
+  // offset is then even, so the pairs are aligned vector loads)
+  const int qv = q / V;
+  for (int k = threadIdx.x; k < m * qv; k += blockDim.x) {
+    const int i = k / qv, t = (k - i * qv) * V;
+    const Vec<T, V> xv = ldv<T, V>(tr + t), cv = ldv<T, V>(tr + 3 * q + t), yv = ldv<T, V>(tr + 4 * q + t),
+                    sv = ldv<T, V>(tr + 7 * q + t);
+    const Vec<T, V> uxv = slack ? cv : ldv<T, V>(p3 + q + t), uyv = slack ? sv : ldv<T, V>(p3 + 2 * q + t);
     const T ri = T(D.r[i]);
     const size_t base = (size_t(l) * m + i) * n * q + t;
     const T *al = w.alpha + base, *dd = w.d + base;
@@ -313,28 +327,50 @@ __global__ __launch_bounds__(kItemThreads) void k_targets(Desc D, Ptrs<T> w) {
     // outside the ellipse and is its own target (eqs. zeta_2,
     // compute_zeta_3), so the deviation is exactly zero; the literal angle
     // has no such fixed points.
-    T sx = 0, sy = 0;
+    T sx[V], sy[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) sx[e] = sy[e] = T(0);
     const T *oxt = ox + t, *oyt = oy + t;
     // a chunk of d_ij in one memory latency; colliding rows (d_ij <= 1, a
     // few percent) then load their angle and obstacle position
     for (int j0 = 0; j0 < n; j0 += kTgtChunk<T>) {
-      T dv[kTgtChunk<T>];
+      Vec<T, V> dv[kTgtChunk<T>];
 #pragma unroll
-      for (int u = 0; u < kTgtChunk<T>; ++u) dv[u] = j0 + u < n ? dd[size_t(j0 + u) * q] : T(2);
+      for (int u = 0; u < kTgtChunk<T>; ++u) {
+        if (j0 + u < n) {
+          dv[u] = ldv<T, V>(dd + size_t(j0 + u) * q);
+        } else {
+#pragma unroll
+          for (int e = 0; e < V; ++e) dv[u].v[e] = T(2);
+        }
+      }
 #pragma unroll
       for (int u = 0; u < kTgtChunk<T>; ++u) {
         const int j = j0 + u;
-        if (j < n && (literal || dv[u] <= T(1))) {
-          const T oxj = oxt[j * q] - T(D.offx), oyj = oyt[j * q] - T(D.offy);
-          T sa, ca;
-          Num<T>::sincos_(al[size_t(j) * q], &sa, &ca);
-          sx += ell[0][j] * dv[u] * ca - (x + ri * ux - oxj);
-          sy += ell[1][j] * dv[u] * sa - (y + ri * uy - oyj);
+        bool hit = literal;
+#pragma unroll
+        for (int e = 0; e < V; ++e) hit |= dv[u].v[e] <= T(1);
+        if (j < n && hit) {
+          const Vec<T, V> av = ldv<T, V>(al + size_t(j) * q), gx = ldv<T, V>(oxt + j * q),
+                          gy = ldv<T, V>(oyt + j * q);
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            if (literal || dv[u].v[e] <= T(1)) {
+              const T oxj = gx.v[e] - T(D.offx), oyj = gy.v[e] - T(D.offy);
+              T sa, ca;
+              Num<T>::sincos_(av.v[e], &sa, &ca);
+              sx[e] += ell[0][j] * dv[u].v[e] * ca - (xv.v[e] + ri * uxv.v[e] - oxj);
+              sy[e] += ell[1][j] * dv[u].v[e] * sa - (yv.v[e] + ri * uyv.v[e] - oyj);
+            }
+          }
         }
       }
     }
-    part[0][k] = sx;
-    part[1][k] = sy;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      part[0][i * q + t + e] = sx[e];
+      part[1][i * q + t + e] = sy[e];
+    }
   }
   // inputs of the channels at t = threadIdx.x, loaded before the barrier so
   // that their latency overlaps the wait (q <= blockDim.x whenever m q fits
@@ -642,6 +678,14 @@ void xi1(const Desc &D, const Ptrs<T> &w, hipStream_t st) {
   hipLaunchKernelGGL((k_xi1<T, NV>), dim3(blocks_for(size_t(D.B) * 4 * NV)), dim3(kThreads), 0, st, D, w);
 }
 
+template <typename T>
+void targets(const Desc &D, const Ptrs<T> &w, hipStream_t st) {
+  if (D.q % 2 == 0)
+    hipLaunchKernelGGL((k_targets<T, 2>), dim3(D.B), dim3(item_threads(D.m * D.q / 2)), 0, st, D, w);
+  else
+    hipLaunchKernelGGL((k_targets<T, 1>), dim3(D.B), dim3(item_threads(D.m * D.q)), 0, st, D, w);
+}
+
 template <typename T, int NV>
 hipError_t run(const Desc &D, void *ws, hipStream_t st) {
   const PlainWs L = plain_layout(D.B, D.q, NV, D.m, D.n);
@@ -653,14 +697,14 @@ hipError_t run(const Desc &D, void *ws, hipStream_t st) {
   hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
   hipLaunchKernelGGL((k_eval_psi<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
   hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(size_t(B) * (D.m + 1) * q)), dim3(kThreads), 0, st, D, w);
-  hipLaunchKernelGGL((k_targets<T>), dim3(B), dim3(item_threads(D.m * q)), 0, st, D, w);
+  targets<T>(D, w, st);
   contract<T, NV>(D, w, st, 0);
   for (int it = 0; it < D.K; ++it) {
     xi1<T, NV>(D, w, st);
     hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_xi2<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(size_t(B) * (D.m + 1) * q)), dim3(kThreads), 0, st, D, w);
-    hipLaunchKernelGGL((k_targets<T>), dim3(B), dim3(item_threads(D.m * q)), 0, st, D, w);
+    targets<T>(D, w, st);
     contract<T, NV>(D, w, st, 1);
   }
   const size_t exit_work = std::max(size_t(B) * 5 * NV, size_t(B) * q);

@@ -142,6 +142,7 @@ struct am_server {
   std::unordered_map<int, int64_t> client_busy;  // client -> ticket in flight
   int64_t next_ticket = 0, completed = 0, launches = 0, memory_waits = 0, evictions = 0;
   bool stop = false;
+  Clock::time_point last_activity = Clock::now();   // last launch, retirement or submission
   std::string error;
   std::thread worker;
   // KKT cache: handles built for requests that name a shape instead of a
@@ -282,14 +283,18 @@ int am_server::launch(Slot &slot) {
     const am_state st = state_of(this, r, r->state);
     const size_t coef = size_t(r->B) * r->nv * es;
     char *s0 = stage;
+    // [B][5][nv] doubles -> [5][B][nv] in the solve's precision
     for (int v = 0; v < 5; ++v)
-      for (int l = 0; l < r->B; ++l)
-        for (int k = 0; k < r->nv; ++k) {
-          const double val = r->init[(size_t(l) * 5 + v) * r->nv + k];
-          if (f64) reinterpret_cast<double *>(stage)[0] = val;
-          else reinterpret_cast<float *>(stage)[0] = float(val);
-          stage += es;
+      for (int l = 0; l < r->B; ++l) {
+        const double *src = r->init.data() + (size_t(l) * 5 + v) * r->nv;
+        if (f64) {
+          std::memcpy(stage, src, size_t(r->nv) * sizeof(double));
+        } else {
+          float *dst = reinterpret_cast<float *>(stage);
+          for (int k = 0; k < r->nv; ++k) dst[k] = float(src[k]);
         }
+        stage += size_t(r->nv) * es;
+      }
     auto wit = r->warm_src;
     if (wit.live) {
       if (hipMemcpyAsync(st.cx, s0, 5 * coef, hipMemcpyHostToDevice, slot.stream) != hipSuccess) return AM_ERR_HIP;
@@ -396,9 +401,21 @@ void am_server::run() {
     bool busy = false;
     for (Slot &s : slots) busy |= s.busy;
     if (stop && !busy && pending.empty()) break;
+    const auto now = Clock::now();
+    if (progressed) last_activity = now;
     if (!progressed) {
-      if (busy) cv_work.wait_for(lk, std::chrono::microseconds(20));
-      else cv_work.wait_for(lk, std::chrono::milliseconds(5));
+      const bool spin = busy || std::chrono::duration_cast<std::chrono::microseconds>(now - last_activity).count() <
+                                    cfg.idle_spin_us;
+      if (spin) {
+        // work in flight (or the idle-spin window): poll without sleeping (a
+        // timed wait would add the scheduler's timer slack to every
+        // completion, a wake-up the OS wake-up time to every arrival)
+        lk.unlock();
+        std::this_thread::yield();
+        lk.lock();
+      } else {
+        cv_work.wait_for(lk, std::chrono::milliseconds(5));
+      }
     }
   }
 }
@@ -416,6 +433,8 @@ int am_server_create(const am_server_config *cfg, am_server **out) {
   if (cfg->max_per_launch < 1 || cfg->max_per_launch > kMaxPerLaunch)
     return srv_fail(AM_ERR_INVALID, "max_per_launch must be 1..256");
   if (cfg->select_best && !(cfg->fc_tol >= 0.0)) return srv_fail(AM_ERR_INVALID, "fc_tol must be >= 0");
+  if (cfg->idle_spin_us < 0 || cfg->idle_spin_us > 1000000)
+    return srv_fail(AM_ERR_INVALID, "idle_spin_us must be 0..1000000");
   auto *s = new am_server();
   s->cfg = *cfg;
   if (cfg->mode != AM_SERVE_CONTINUOUS) { s->cfg.streams = 1; s->cfg.max_per_launch = 1; }

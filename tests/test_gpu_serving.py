@@ -42,7 +42,8 @@ def test_same_result_alone_and_in_the_mix(am):
     done, _, alone = s1.wait(t, 60.0, traj=True)
     assert done
     s1.close()
-    s2 = am.Server(1 << 28, streams=4, max_per_launch=16)
+    # the mix on a server that polls between arrivals (idle-spin window)
+    s2 = am.Server(1 << 28, streams=4, max_per_launch=16, idle_spin_us=5000)
     tickets = [s2.submit(h, c["problem"], i, c["batch"], K, c["init"]) for i, (h, c) in enumerate(zip(hs, clients))]
     outs = [s2.wait(tk, 60.0, traj=True) for tk in tickets]
     assert all(o[0] for o in outs)

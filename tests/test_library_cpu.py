@@ -83,7 +83,8 @@ def test_null_arguments_rejected(amlib):
 
 
 @pytest.mark.parametrize("bad", [dict(hbm_budget=0), dict(streams=0), dict(streams=17), dict(max_per_launch=0),
-                                 dict(max_per_launch=257), dict(mode=3), dict(dtype=2)])
+                                 dict(max_per_launch=257), dict(mode=3), dict(dtype=2), dict(idle_spin_us=-1),
+                                 dict(idle_spin_us=1000001)])
 def test_server_rejects_bad_config(amlib, bad):
     L = amlib.lib()
     c = amlib.ServerConfig()
