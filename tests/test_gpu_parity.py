@@ -196,6 +196,31 @@ def test_residuals_match_oracle():
     np.testing.assert_allclose(res, ref, atol=1e-7, rtol=1e-6)
 
 
+def _odd_horizon_problem(q, B=5):
+    import dataclasses
+    cfg = dataclasses.replace(inputs.CONFIGS["c2"], q=q)
+    pb = inputs.make_problem(cfg, 11)
+    return pb, inputs.make_initial(pb, B, 12, cfg.sigma)
+
+
+@pytest.mark.parametrize("q", [37, 65, 127])
+@pytest.mark.parametrize("plain", [False, True])
+def test_odd_horizon_f64(q, plain):
+    """An odd number of time steps: the fused kernel's two halves differ in
+    length and the plain target kernel takes its one-step-per-item path."""
+    pb, init = _odd_horizon_problem(q)
+    _compare_f64(pb, init, 8, plain=plain)
+
+
+def test_residuals_odd_horizon():
+    from paper_2109_13030_amd import am
+    pb, init = _odd_horizon_problem(37, B=6)
+    h, p, st = H.run_gpu(pb, init, 10, "f64")
+    res = am.residuals(h, p, st).cpu().numpy()
+    orc, ost = H.run_oracle(pb, init, 10)
+    np.testing.assert_allclose(res, orc.residuals(ost), atol=1e-7, rtol=1e-6)
+
+
 def test_multi_problem_launch_equals_single_launches():
     """Uneven problems in one launch give bit-identical results to one launch
     per problem (same kernel, same arithmetic)."""
