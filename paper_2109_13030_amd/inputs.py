@@ -8,7 +8,7 @@ oracle-based tests, so that both see identical inputs.
 Workloads follow the paper's setting (Sec. II-B, Sec. IV): a rectangular
 holonomic robot covered by ``m`` overlapping circles, ``n`` axis-aligned
 elliptical obstacles (static or moving at constant velocity), a 30 s horizon
-("around 30s", Sec. II-B), boundary conditions shared by the whole batch, and
+(the paper gives about 30 s, Sec. II-B), boundary conditions shared by the whole batch, and
 initial trajectories drawn once from a Gaussian around a straight line
 (Sec. IV, implementation details).  The paper's crowd scenes are not
 available; these seeded draws stand in for them.
