@@ -214,7 +214,12 @@ def run_serving(rates, n_requests, modes=("continuous", "plain"), n_clients: int
         arr = inputs.poisson_arrivals(rate, count, rseed) if rate else np.zeros(count)
         work, tickets = 0, []
         t0 = time.perf_counter()
+        t_note = t0
         for ta in arr:
+            if time.perf_counter() - t_note > 60.0:
+                t_note = time.perf_counter()
+                print(f"serving {mode} {rate:g} Hz: {len(tickets)} of {count} requests submitted",
+                      file=sys.stderr, flush=True)
             while True:
                 now = time.perf_counter() - t0
                 if now >= ta:
@@ -421,7 +426,26 @@ def cpu_baseline(pb, init, K, seconds: float):
     rec = {"value": sample * K / dt, "unit": "traj-AM-iter/s", "cores": threads, "kind": "oracle",
            "sample": f"first {sample} of {B} trajectories of the same workload, {K} iterations each, "
                      f"FP64, OpenMP over trajectories ({dt:.1f} s)"}
+    # one thread on a few trajectories, and what the host is
+    few = min(B, 16)
+    st1 = oracle.state_from(pb, {k: np.asarray(v)[:few] for k, v in init.items()})
+    t0 = time.perf_counter()
+    orc.solve(st1, K, nthreads=1)
+    rec["single_thread_value"] = few * K / (time.perf_counter() - t0)
+    rec["single_thread_sample"] = f"first {few} trajectories, one thread"
+    rec["cpu_model"] = cpu_model()
+    rec["nproc"] = os.cpu_count()
     return rec, st
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def error_vs_oracle(pb, gpu: dict, orc_state: dict):
@@ -453,6 +477,8 @@ def main():
                     help="run only the replanning (serving) workload at 50/100/200 Hz and print its JSON")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of each Poisson run of --serve (requests = rate x seconds)")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="with --serve: requests per arrival rate (default: rate x --serve-seconds)")
     ap.add_argument("--uneven", action="store_true", help="run only the 64-problem uneven workload (c3)")
     ap.add_argument("--precision", action="store_true",
                     help="run only the precision workload (c4): FP32 vs BF16-split contraction, errors vs oracle")
@@ -474,11 +500,16 @@ def main():
         import torch
         x = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
-        for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2):
             torch.mul(x, 1.0, out=y)
+        e1.record()
         torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 2
         print(json.dumps({"copy_ref_bytes_read": x.numel() * 4, "copy_ref_bytes_written": y.numel() * 4,
-                          "launches": 3}))
+                          "launches": 3, "copy_ms": ms, "copy_GBps": 2 * x.numel() * 4 / (ms * 1e-3) / 1e9}))
         return
     if args.uneven:
         print(json.dumps(run_uneven()), flush=True)
@@ -501,7 +532,8 @@ def main():
               flush=True)
         return
     if args.serve:
-        print(json.dumps(run_serving((50.0, 100.0, 200.0), lambda r: int(r * args.serve_seconds), saturation=256)),
+        count = (lambda r: args.serve_requests) if args.serve_requests else (lambda r: int(r * args.serve_seconds))
+        print(json.dumps(run_serving((50.0, 100.0, 200.0), count, saturation=256)),
               flush=True)
         return
     out, pb, init, K = run_gpu(args)
