@@ -678,9 +678,16 @@ void xi1(const Desc &D, const Ptrs<T> &w, hipStream_t st) {
   hipLaunchKernelGGL((k_xi1<T, NV>), dim3(blocks_for(size_t(D.B) * 4 * NV)), dim3(kThreads), 0, st, D, w);
 }
 
+// Four time steps per item once the batch gives every SIMD about four
+// wavefronts of them (fewer, wider loads); two below that, where more
+// wavefronts hide more latency.
+constexpr size_t kWideItems = size_t(256) * 4 * 64 * 4;
+
 template <typename T>
 void targets(const Desc &D, const Ptrs<T> &w, hipStream_t st) {
-  if (D.q % 2 == 0)
+  if (D.q % 4 == 0 && sizeof(T) == 4 && size_t(D.B) * D.m * D.q / 4 >= kWideItems)
+    hipLaunchKernelGGL((k_targets<T, 4>), dim3(D.B), dim3(item_threads(D.m * D.q / 4)), 0, st, D, w);
+  else if (D.q % 2 == 0)
     hipLaunchKernelGGL((k_targets<T, 2>), dim3(D.B), dim3(item_threads(D.m * D.q / 2)), 0, st, D, w);
   else
     hipLaunchKernelGGL((k_targets<T, 1>), dim3(D.B), dim3(item_threads(D.m * D.q)), 0, st, D, w);
