@@ -150,7 +150,8 @@ def run_gpu(args):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
                      "traffic": measured_traffic(args.workload) if dtype == "f32" else None,
-                     "kernel": f"fused_kernel<{'float' if dtype == 'f32' else 'double'},{nv},{tile},{waves}>",
+                     "kernel": f"fused_kernel<{'float' if dtype == 'f32' else 'double'},{nv},"
+                               f"{5 if m <= 5 and dtype == 'f32' else 8},{tile},{waves}>",
                      "kernel_ms": avg_kernel_s * 1e3, "tile": tile, "waves_per_simd": waves,
                      "autotune_ms": {f"tile{k[0]}_waves{k[1]}": round(v, 4) for k, v in tile_ms.items()},
                      "flop_per_launch": flops,

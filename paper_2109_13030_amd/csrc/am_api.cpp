@@ -303,7 +303,7 @@ int am_solve_batch(am_handle *h, const am_problem *p, int32_t batch, int32_t ite
   const size_t lds = amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64, h->tile, h->waves);
   if (lds > lds_limit())
     return fail(AM_ERR_INVALID, "problem needs %zu bytes of LDS, device allows %zu", lds, lds_limit());
-  hipError_t e = amk::launch_fused(d, nullptr, 1, d.nblk, h->f64, h->shape.nv,
+  hipError_t e = amk::launch_fused(d, nullptr, 1, d.nblk, h->f64, h->shape.nv, h->shape.m,
                                    static_cast<hipStream_t>(stream), lds, h->tile, h->waves);
   if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
   return AM_OK;
@@ -334,7 +334,7 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
   const am_handle *h0 = handles[0];
   if (!h0) return fail(AM_ERR_INVALID, "handle 0 is NULL");
   size_t lds = 0;
-  int blocks = 0;
+  int blocks = 0, max_m = 1;
   for (int k = 0; k < nprob; ++k) {
     const am_handle *h = handles[k];
     if (!h) return fail(AM_ERR_INVALID, "handle %d is NULL", k);
@@ -350,6 +350,7 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
     blocks += d.nblk;
     descs.push_back(d);
     lds = std::max(lds, amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64, h0->tile, h0->waves));
+    max_m = std::max(max_m, int(h->shape.m));
   }
   if (lds > lds_limit())
     return fail(AM_ERR_INVALID, "a problem needs %zu bytes of LDS, device allows %zu", lds, lds_limit());
@@ -358,7 +359,7 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
   Desc *table = static_cast<Desc *>(workspace);
   hipError_t e = amk::launch_desc_copy(descs.data(), nprob, table, s);
   if (e != hipSuccess) return hip_fail(e, "problem table copy");
-  e = amk::launch_fused(descs[0], table, nprob, blocks, h0->f64, h0->shape.nv, s, lds, h0->tile, h0->waves);
+  e = amk::launch_fused(descs[0], table, nprob, blocks, h0->f64, h0->shape.nv, max_m, s, lds, h0->tile, h0->waves);
   if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
   return AM_OK;
 }

@@ -45,7 +45,9 @@
 namespace amk {
 namespace {
 
-constexpr int kMaxC = AM_MAX_CIRCLES;
+// Circle capacity of a kernel instance: 5 (enough for every robot shape
+// here; fewer registers and no dead circle slots) or AM_MAX_CIRCLES.
+constexpr int kSmallC = 5;
 constexpr int kVoteChunk = 8;   // obstacles whose positions are loaded together in the vote
 constexpr double kVoteMargin = 0.25;   // [m] slack of the near-obstacle set, see project_reduce
 
@@ -169,7 +171,7 @@ __device__ __forceinline__ T row_dot_reg(const T (&r)[pad4(2 * NV)], const T *v)
   return acc0 + acc1;
 }
 
-template <typename T, int NV, int RED>
+template <typename T, int NV, int C, int RED>
 __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds, const FusedLds &L,
                            int lane, int wave) {
   constexpr int A2 = pad4(2 * NV), N2 = 2 * NV;
@@ -204,10 +206,10 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   T *xch = lds + L.xch + (wave >> 1) * 2 * kXchHalf;
   T *xmine = xch + half * kXchHalf;
 
-  T rr[kMaxC];
+  T rr[C];
   T s1 = T(0), s2 = T(0), rmax = T(0);
 #pragma unroll
-  for (int i = 0; i < kMaxC; ++i) {
+  for (int i = 0; i < C; ++i) {
     rr[i] = i < m ? uni(T(Dsrc.r[i])) : T(0);
     s1 += rr[i];
     s2 += rr[i] * rr[i];
@@ -314,11 +316,11 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // (fast form; a non-finite sum, as from a zero or subnormal r2, is redone
   // element by element afterwards).
   // p = (a^2, b^2, ab, max(a, b)) of the inflated ellipse.
-  T Sx[kMaxC], Sy[kMaxC];
+  T Sx[C], Sy[C];
   auto project_obstacle = [&](T ux, T uy, const Pair<T> o, const Quad<T> p) {
     const T dxj = x - o.x, dyj = y - o.y;
 #pragma unroll
-    for (int i = 0; i < kMaxC; ++i) {
+    for (int i = 0; i < C; ++i) {
       if (i < m) {
         const T xt = dxj + rr[i] * ux, yt = dyj + rr[i] * uy;
         const T r2 = p.b * xt * xt + p.a * yt * yt;   // b^2 x~^2 + a^2 y~^2
@@ -342,7 +344,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   auto project_reduce = [&](bool with_psi) {
     const T ux = slack ? cc : cps, uy = slack ? ss : sps;
 #pragma unroll
-    for (int i = 0; i < kMaxC; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
+    for (int i = 0; i < C; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
     if (!literal_alpha) {
       // Wave-wide vote: obstacles within ext + max(a, b) + margin of some
       // lane's robot centre, ext = max|r_i| |u| the reach of its circles.
@@ -409,7 +411,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
         const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
         const T a2 = op[j * 8 + OP_A2], b2 = op[j * 8 + OP_B2];
 #pragma unroll
-        for (int i = 0; i < kMaxC; ++i) {
+        for (int i = 0; i < C; ++i) {
           if (i < m) {
             const T xt = x + rr[i] * ux - o.x, yt = y + rr[i] * uy - o.y;
             const T xx = xt * xt, yy = yt * yt;
@@ -424,7 +426,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     auto sum_circles = [&]() {
       Dx = Dy = DRx = DRy = T(0);
 #pragma unroll
-      for (int i = 0; i < kMaxC; ++i) {
+      for (int i = 0; i < C; ++i) {
         Dx += Sx[i]; Dy += Sy[i];
         DRx += rr[i] * Sx[i]; DRy += rr[i] * Sy[i];
       }
@@ -435,7 +437,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     // those circles' sums element by element (alpha := 0 at the zero vector).
     if (__ballot(!(isfinite(Dx) && isfinite(Dy))) != 0) {
 #pragma unroll
-      for (int i = 0; i < kMaxC; ++i) {
+      for (int i = 0; i < C; ++i) {
         if (i < m && !(isfinite(Sx[i]) && isfinite(Sy[i]))) {
           T sx = T(0), sy = T(0);
           for (int j = 0; j < n; ++j) {
@@ -645,7 +647,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 }
 
 // One block: LDS set-up shared by the block's trajectories, then the loop.
-template <typename T, int NV, int TILE, int WAVES>
+template <typename T, int NV, int C, int TILE, int WAVES>
 __device__ __forceinline__ void fused_block(const Desc &D) {
   constexpr int RED = red_rows_for(WAVES);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -684,21 +686,21 @@ __device__ __forceinline__ void fused_block(const Desc &D) {
   // trajectory and stores nothing.
   const int lt = (int(blockIdx.x) - blk0) * TILE + (wave >> 1);
   const bool live = lt < B;
-  fused_body<T, NV, RED>(D, live ? lt : B - 1, live, wave & 1, lds, L, lane, wave);
+  fused_body<T, NV, C, RED>(D, live ? lt : B - 1, live, wave & 1, lds, L, lane, wave);
 }
 
 // One problem: the descriptor travels as a kernel argument.  WAVES is the
 // register budget: at least that many wavefronts per SIMD (1: up to 512
 // VGPRs and AGPRs, 2: up to 256, 3: up to 168).
-template <typename T, int NV, int TILE, int WAVES>
+template <typename T, int NV, int C, int TILE, int WAVES>
 __global__ __launch_bounds__(kWave * 2 * TILE) __attribute__((amdgpu_waves_per_eu(WAVES)))
 void fused_kernel(Desc single) {
-  fused_block<T, NV, TILE, WAVES>(single);
+  fused_block<T, NV, C, TILE, WAVES>(single);
 }
 
 // Several problems: block b belongs to the last problem whose first block is
 // <= b (binary search of the table in global memory).
-template <typename T, int NV, int TILE, int WAVES>
+template <typename T, int NV, int C, int TILE, int WAVES>
 __global__ __launch_bounds__(kWave * 2 * TILE) __attribute__((amdgpu_waves_per_eu(WAVES)))
 void fused_multi_kernel(const Desc *__restrict__ table, int nprob) {
   int lo = 0, hi = nprob - 1;
@@ -706,36 +708,45 @@ void fused_multi_kernel(const Desc *__restrict__ table, int nprob) {
     const int mid = (lo + hi + 1) >> 1;
     if (uni(table[mid].blk0) <= int(blockIdx.x)) lo = mid; else hi = mid - 1;
   }
-  fused_block<T, NV, TILE, WAVES>(table[uni(lo)]);
+  fused_block<T, NV, C, TILE, WAVES>(table[uni(lo)]);
 }
 
-template <typename T, int NV, int TILE, int WAVES>
+template <typename T, int NV, int C, int TILE, int WAVES>
 hipError_t launch_t(const Desc &single, const Desc *table, int nprob, int nblocks, hipStream_t st,
                     size_t lds_bytes) {
-  const void *fn = table ? reinterpret_cast<const void *>(&fused_multi_kernel<T, NV, TILE, WAVES>)
-                         : reinterpret_cast<const void *>(&fused_kernel<T, NV, TILE, WAVES>);
+  const void *fn = table ? reinterpret_cast<const void *>(&fused_multi_kernel<T, NV, C, TILE, WAVES>)
+                         : reinterpret_cast<const void *>(&fused_kernel<T, NV, C, TILE, WAVES>);
   if (lds_bytes > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
     if (e != hipSuccess) return e;
   }
   if (table)
-    hipLaunchKernelGGL((fused_multi_kernel<T, NV, TILE, WAVES>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes,
-                       st, table, nprob);
+    hipLaunchKernelGGL((fused_multi_kernel<T, NV, C, TILE, WAVES>), dim3(nblocks), dim3(kWave * 2 * TILE),
+                       lds_bytes, st, table, nprob);
   else
-    hipLaunchKernelGGL((fused_kernel<T, NV, TILE, WAVES>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes, st,
-                       single);
+    hipLaunchKernelGGL((fused_kernel<T, NV, C, TILE, WAVES>), dim3(nblocks), dim3(kWave * 2 * TILE), lds_bytes,
+                       st, single);
   return hipGetLastError();
 }
 
-template <typename T, int NV, int WAVES>
+template <typename T, int NV, int C, int WAVES>
 hipError_t launch_tile(const Desc &single, const Desc *table, int nprob, int nblocks, hipStream_t st,
                        size_t lds_bytes, int tile) {
   switch (tile) {
-    case 1: return launch_t<T, NV, 1, WAVES>(single, table, nprob, nblocks, st, lds_bytes);
-    case 2: return launch_t<T, NV, 2, WAVES>(single, table, nprob, nblocks, st, lds_bytes);
-    case 4: return launch_t<T, NV, 4, WAVES>(single, table, nprob, nblocks, st, lds_bytes);
+    case 1: return launch_t<T, NV, C, 1, WAVES>(single, table, nprob, nblocks, st, lds_bytes);
+    case 2: return launch_t<T, NV, C, 2, WAVES>(single, table, nprob, nblocks, st, lds_bytes);
+    case 4: return launch_t<T, NV, C, 4, WAVES>(single, table, nprob, nblocks, st, lds_bytes);
     default: return hipErrorInvalidValue;
   }
+}
+
+// FP32: the small circle capacity when every problem of the launch fits it.
+template <int NV, int WAVES>
+hipError_t launch_f32(const Desc &single, const Desc *table, int nprob, int nblocks, hipStream_t st,
+                      size_t lds_bytes, int tile, int max_m) {
+  if (max_m <= kSmallC)
+    return launch_tile<float, NV, kSmallC, WAVES>(single, table, nprob, nblocks, st, lds_bytes, tile);
+  return launch_tile<float, NV, AM_MAX_CIRCLES, WAVES>(single, table, nprob, nblocks, st, lds_bytes, tile);
 }
 
 }  // namespace
@@ -747,18 +758,20 @@ size_t fused_lds_bytes(int q, int n, int nv, bool f64, int tile, int waves) {
 // FP64 kernels take the default budget only, built without a wavefront
 // target (their registers do not fit 256 without spilling).
 hipError_t launch_fused(const Desc &single, const Desc *table, int nprob, int nblocks, bool f64,
-                        int nv, hipStream_t st, size_t lds_bytes, int tile, int waves) {
+                        int nv, int max_m, hipStream_t st, size_t lds_bytes, int tile, int waves) {
   if (nblocks <= 0) return hipSuccess;
+  if (max_m < 1 || max_m > AM_MAX_CIRCLES) return hipErrorInvalidValue;
+  constexpr int MC = AM_MAX_CIRCLES;
   if (f64) {
     if (waves != 2) return hipErrorInvalidValue;
-    if (nv == 11) return launch_tile<double, 11, 1>(single, table, nprob, nblocks, st, lds_bytes, tile);
-    if (nv == 8) return launch_tile<double, 8, 1>(single, table, nprob, nblocks, st, lds_bytes, tile);
+    if (nv == 11) return launch_tile<double, 11, MC, 1>(single, table, nprob, nblocks, st, lds_bytes, tile);
+    if (nv == 8) return launch_tile<double, 8, MC, 1>(single, table, nprob, nblocks, st, lds_bytes, tile);
   } else if (waves == 2) {
-    if (nv == 11) return launch_tile<float, 11, 2>(single, table, nprob, nblocks, st, lds_bytes, tile);
-    if (nv == 8) return launch_tile<float, 8, 2>(single, table, nprob, nblocks, st, lds_bytes, tile);
+    if (nv == 11) return launch_f32<11, 2>(single, table, nprob, nblocks, st, lds_bytes, tile, max_m);
+    if (nv == 8) return launch_f32<8, 2>(single, table, nprob, nblocks, st, lds_bytes, tile, max_m);
   } else if (waves == 3) {
-    if (nv == 11) return launch_tile<float, 11, 3>(single, table, nprob, nblocks, st, lds_bytes, tile);
-    if (nv == 8) return launch_tile<float, 8, 3>(single, table, nprob, nblocks, st, lds_bytes, tile);
+    if (nv == 11) return launch_f32<11, 3>(single, table, nprob, nblocks, st, lds_bytes, tile, max_m);
+    if (nv == 8) return launch_f32<8, 3>(single, table, nprob, nblocks, st, lds_bytes, tile, max_m);
   }
   return hipErrorInvalidValue;
 }

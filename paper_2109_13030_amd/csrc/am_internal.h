@@ -65,8 +65,10 @@ struct Consts {
 hipError_t launch_setup(const am_shape &s, const double *r_dev, const Consts &c, bool f64,
                         hipStream_t st);
 size_t fused_lds_bytes(int q, int n, int nv, bool f64, int tile, int waves);
+// max_m: the largest circle count of the launch's problems (picks the
+// kernel's circle capacity)
 hipError_t launch_fused(const Desc &single, const Desc *table, int nprob, int nblocks, bool f64,
-                        int nv, hipStream_t st, size_t lds_bytes, int tile, int waves);
+                        int nv, int max_m, hipStream_t st, size_t lds_bytes, int tile, int waves);
 hipError_t launch_select_best(const void *res, int B, double tol, int32_t *idx, void *vals, bool f64,
                               hipStream_t st);
 hipError_t launch_residuals(const Desc &d, const void *P, const void *Pd, const void *Pdd, void *out,

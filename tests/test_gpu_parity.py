@@ -164,6 +164,17 @@ def test_c1_f32_matches_oracle():
     _fp32_gate(pb, init, 50)
 
 
+@pytest.mark.parametrize("m", [1, 6, 8])
+def test_f32_circle_counts_against_oracle(m):
+    """FP32 with 1, 6 and 8 circles: the kernel instance with room for five
+    circles (m <= 5) and the one with room for eight."""
+    import dataclasses
+    cfg = dataclasses.replace(inputs.CONFIGS["c2"], circles=m)
+    pb = inputs.make_problem(cfg, 21)
+    init = inputs.make_initial(pb, 24, 22, cfg.sigma)
+    _fp32_gate(pb, init, 30)
+
+
 def test_c2_f32_full_batch_sampled_against_oracle():
     """Config c2 at its full size (B = 1000, 5 circles, 10 moving obstacles,
     100 iterations) in the launch the benchmark times; 48 sampled
