@@ -157,6 +157,8 @@ def run_gpu(args):
                      "flop_per_launch": flops,
                      "hbm_bytes_per_launch": bytes_per_launch(q, nv, m, n, B, K)},
         "step_ms_events": float(np.mean(step_ms)),
+        "step_ms_median": float(np.median(step_ms)),
+        "solve_ms_median": float(np.median(solve_ms)),
         "final_residuals": {"fc_max_median": float(np.median(res[:, 0])),
                             "bc_max": float(res[:, 6].max()),
                             "nonfinite": int(res[:, 11].max())},
