@@ -142,3 +142,67 @@ class PaperProblem:
             return 0.5 * np.sum((self.Pdd @ c) ** 2) - lp @ c + 0.5 * rho * np.sum((ph - self.P @ c) ** 2)
         H, g = quad_parts(J, self.nv)
         return nullspace_qp(H, g, self.A, np.asarray(self.pb["bpsi"], float))
+
+    # --- the remaining steps of Sec. III-D, written independently -----------
+    def project(self, st, l):
+        """xi3, xi4 of trajectory l (eqs. zeta_2, compute_zeta_3, alpha_v,
+        alpha_a, compute_dv, compute_da) from its current coefficients, with
+        the readings the oracle takes: elliptic angle unless the literal flag,
+        x~ from cos psi unless the slack flag, d by the ratio form, angle 0 at
+        the zero vector, d_v and d_a clipped to [0, 1]."""
+        P, Pd, Pdd = self.P, self.Pd, self.Pdd
+        x, y = P @ st["cx"][l], P @ st["cy"][l]
+        psi = P @ st["cpsi"][l]
+        if self.flags & 2:
+            ux, uy = P @ st["cc"][l], P @ st["cs"][l]
+        else:
+            ux, uy = np.cos(psi), np.sin(psi)
+        for i in range(self.m):
+            for j in range(self.n):
+                a, b = self.a[j], self.b[j]
+                xt = x + self.r[i] * ux - self.ox[j]
+                yt = y + self.r[i] * uy - self.oy[j]
+                al = atan2z(yt, xt) if self.flags & 1 else atan2z(a * yt, b * xt)
+                ca, sa = np.cos(al), np.sin(al)
+                d = (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa)
+                e = i * self.n + j
+                st["alpha"][l, e] = al
+                st["d"][l, e] = np.maximum(1.0, d)
+        for (vx, vy, lim, ka, kd) in ((Pd @ st["cx"][l], Pd @ st["cy"][l], self.pb["vmax"], "av", "dv"),
+                                      (Pdd @ st["cx"][l], Pdd @ st["cy"][l], self.pb["amax"], "aa", "da")):
+            al = atan2z(vy, vx)
+            st[ka][l] = al
+            st[kd][l] = np.clip((vx * np.cos(al) + vy * np.sin(al)) / lim, 0.0, 1.0)
+
+    def lambda_update(self, st, l):
+        """eq. update_lambda_1 as the gradient step of the row-wise penalty
+        (its rows are affine in xi, so the Jacobian is exact), and eq.
+        update_lambda_psi with the reading's sign."""
+        nv, rho = self.nv, self.pb["rho"]
+        psi = self.P @ st["cpsi"][l]
+        for axis in (0, 1):
+            xi = np.concatenate([st["cx" if axis == 0 else "cy"][l], st["cc" if axis == 0 else "cs"][l]])
+            r0 = self.penalty_rows(np.zeros(2 * nv), axis, st, l, psi)
+            J = np.stack([self.penalty_rows(e, axis, st, l, psi) - r0 for e in np.eye(2 * nv)], axis=1)
+            grad = J.T @ self.penalty_rows(xi, axis, st, l, psi)
+            st["lam"][l, axis * 2 * nv:(axis + 1) * 2 * nv] -= rho * grad
+        sign = -1.0 if self.flags & 8 else 1.0
+        st["lampsi"][l] -= sign * self.pb["rho_psi"] * (self.P.T @ (psi - st["psihat"][l]))
+
+    def am_solve(self, st, K):
+        """The AM list of Sec. III-D for every trajectory, in place: the
+        initial xi3, xi4, then K times xi1, xi2, xi3, xi4 and the
+        multipliers."""
+        B, nv = st["cx"].shape[0], self.nv
+        for l in range(B):
+            self.project(st, l)
+        for _ in range(K):
+            for l in range(B):
+                xi = self.xi1_solution(st, l)
+                st["cx"][l], st["cc"][l] = xi[:nv], xi[nv:2 * nv]
+                st["cy"][l], st["cs"][l] = xi[2 * nv:3 * nv], xi[3 * nv:]
+                ph = self.psi_hat(st, l)
+                st["cpsi"][l] = self.xi2_solution(st, l)
+                st["psihat"][l] = ph
+                self.project(st, l)
+                self.lambda_update(st, l)

@@ -387,6 +387,28 @@ def test_solve_equals_step_sequence():
         np.testing.assert_array_equal(st[k], st2[k])
 
 
+@pytest.mark.parametrize("flags", [0, oracle.XTILDE_SLACK, oracle.ALPHA_LITERAL, oracle.PSI_NO_UNWRAP,
+                                   oracle.LAMPSI_LITERAL, oracle.Q_CS_ZERO])
+def test_solve_equals_independent_composition(flags):
+    """The whole iteration (initial xi3, xi4, then K x (xi1, xi2, xi3, xi4,
+    lambda)) equals the same steps composed from the row-wise objectives,
+    null-space QP solves and closed forms written independently of the
+    oracle, under every reading flag."""
+    pb = tiny_problem(flags=flags)
+    ref = PaperProblem(pb)
+    st = random_state(pb, 2, seed=41)
+    st2 = {k: v.copy() for k, v in st.items()}
+    K = 4
+    oracle.Oracle(pb).solve(st, K)
+    ref.am_solve(st2, K)
+    for k in ("cx", "cc", "cy", "cs", "cpsi"):
+        np.testing.assert_allclose(st[k], st2[k], atol=1e-7, rtol=1e-7, err_msg=k)
+    for k in ("lam", "lampsi"):
+        np.testing.assert_allclose(st[k], st2[k], atol=1e-6 * (1 + np.abs(st2[k]).max()), err_msg=k)
+    np.testing.assert_allclose(np.cos(st["alpha"]), np.cos(st2["alpha"]), atol=1e-7)
+    np.testing.assert_allclose(st["d"], st2["d"], atol=1e-7, rtol=1e-7)
+
+
 def test_invariants_after_solve():
     """After K iterations: BCs exact, d >= 1, d_v and d_a in [0, 1], and each
     trajectory's collision residual no larger than after the first iteration."""
