@@ -409,6 +409,51 @@ def test_solve_equals_independent_composition(flags):
     np.testing.assert_allclose(st["d"], st2["d"], atol=1e-7, rtol=1e-7)
 
 
+def test_residuals_follow_their_definitions():
+    """The oracle's residual statistics equal the same quantities formed from
+    the row-wise constraint residuals of Sec. III-C (obstacle rows: |f_c| per
+    (i, j, t) pair of x and y rows; velocity/acceleration rows; slack rows),
+    the smoothness cost and the boundary rows, all built independently."""
+    pb = tiny_problem()
+    ref = PaperProblem(pb)
+    st = random_state(pb, 3, seed=51)
+    orc = oracle.Oracle(pb)
+    orc.solve(st, 3)
+    res = orc.residuals(st)
+    q, nv, mn = ref.q, ref.nv, ref.m * ref.n
+    for l in range(3):
+        psi = ref.P @ st["cpsi"][l]
+        rows = [ref.penalty_rows(np.concatenate([st[p][l], st[c][l]]), axis, st, l, psi)
+                for axis, (p, c) in enumerate((("cx", "cc"), ("cy", "cs")))]
+        # rows: [velocity q | acceleration q | obstacles m n q | slack q]; the
+        # obstacle rows place the circle with r_i times the slack copies, the
+        # statistic with the heading (cos psi, sin psi) (eq. compute_zeta_33)
+        fc = []
+        for i in range(ref.m):
+            for j in range(ref.n):
+                e = i * ref.n + j
+                x = ref.P @ st["cx"][l] + ref.r[i] * np.cos(psi) - ref.ox[j]
+                y = ref.P @ st["cy"][l] + ref.r[i] * np.sin(psi) - ref.oy[j]
+                fc.append(np.hypot(x - ref.a[j] * st["d"][l, e] * np.cos(st["alpha"][l, e]),
+                                   y - ref.b[j] * st["d"][l, e] * np.sin(st["alpha"][l, e])))
+        fc = np.concatenate(fc)
+        assert fc.shape == (mn * q,)
+        np.testing.assert_allclose(res[l, 0], fc.max(), rtol=1e-12)
+        np.testing.assert_allclose(res[l, 1], np.sqrt(np.mean(fc ** 2)), rtol=1e-12)
+        np.testing.assert_allclose(res[l, 2], np.hypot(rows[0][:q], rows[1][:q]).max(), rtol=1e-10, atol=1e-14)
+        np.testing.assert_allclose(res[l, 3], np.hypot(rows[0][q:2 * q], rows[1][q:2 * q]).max(), rtol=1e-10,
+                                   atol=1e-14)
+        slack = np.maximum(np.abs(rows[0][-q:]), np.abs(rows[1][-q:])).max()
+        np.testing.assert_allclose(res[l, 4], slack, rtol=1e-12)
+        cost = np.sum((ref.Pdd @ st["cx"][l]) ** 2 + (ref.Pdd @ st["cy"][l]) ** 2 + (ref.Pdd @ st["cpsi"][l]) ** 2)
+        np.testing.assert_allclose(res[l, 7], cost, rtol=1e-12)
+        bc = max(np.abs(ref.A @ st["cx"][l] - pb["bx"]).max(), np.abs(ref.A @ st["cy"][l] - pb["by"]).max(),
+                 np.abs(ref.A @ st["cpsi"][l] - pb["bpsi"]).max())
+        np.testing.assert_allclose(res[l, 6], bc, atol=1e-12)
+        speed = np.hypot(ref.Pd @ st["cx"][l], ref.Pd @ st["cy"][l])
+        np.testing.assert_allclose(res[l, 9], (speed - pb["vmax"]).max(), rtol=1e-12)
+
+
 def test_invariants_after_solve():
     """After K iterations: BCs exact, d >= 1, d_v and d_a in [0, 1], and each
     trajectory's collision residual no larger than after the first iteration."""
