@@ -175,6 +175,33 @@ def test_f32_circle_counts_against_oracle(m):
     _fp32_gate(pb, init, 30)
 
 
+def _largest_problem(B):
+    import dataclasses
+    cfg = dataclasses.replace(inputs.CONFIGS["c2"], q=128, n_obs=64, circles=8)
+    pb = inputs.make_problem(cfg, 31)
+    return pb, inputs.make_initial(pb, B, 32, cfg.sigma)
+
+
+def test_largest_sizes_f32():
+    """The largest problem the library takes (AM_MAX_Q, AM_MAX_OBS,
+    AM_MAX_CIRCLES): 128 time steps, 64 obstacles (a full 64-bit vote mask,
+    64 KB of obstacle table in LDS), 8 circles."""
+    pb, init = _largest_problem(6)
+    _fp32_gate(pb, init, 10)
+
+
+def test_largest_sizes_f64_fit_or_clean_error():
+    """FP64 at the largest sizes needs more LDS than a workgroup may hold: the
+    solve either matches the oracle or is refused before any launch with a
+    message that names the LDS need."""
+    from paper_2109_13030_amd import am
+    pb, init = _largest_problem(3)
+    try:
+        _compare_f64(pb, init, 4)
+    except am.AmError as e:
+        assert e.code == am.AM_ERR_INVALID and "LDS" in str(e), str(e)
+
+
 def test_c2_f32_full_batch_sampled_against_oracle():
     """Config c2 at its full size (B = 1000, 5 circles, 10 moving obstacles,
     100 iterations) in the launch the benchmark times; 48 sampled
