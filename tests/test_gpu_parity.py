@@ -190,6 +190,13 @@ def test_largest_sizes_f32():
     _fp32_gate(pb, init, 10)
 
 
+def test_largest_sizes_plain_f64():
+    """The per-sub-step path at the largest sizes (its kernels keep no
+    obstacle table in LDS), FP64 against the oracle."""
+    pb, init = _largest_problem(3)
+    _compare_f64(pb, init, 4, plain=True)
+
+
 def test_largest_sizes_f64_fit_or_clean_error():
     """FP64 at the largest sizes needs more LDS than a workgroup may hold: the
     solve either matches the oracle or is refused before any launch with a
