@@ -40,6 +40,9 @@ struct ResArgs {
   void *out;
 };
 
+template <typename T>
+constexpr T kMinNormal = sizeof(T) == 4 ? T(1.17549435082228750797e-38) : T(2.22507385850720138309e-308);
+
 constexpr int kTrajPerResBlock = kWavesPerBlock / 2;
 constexpr int kResChunk = 4;    // obstacle positions loaded together
 constexpr int kResStats = 10;   // per-wave statistics combined across the pair
@@ -76,6 +79,10 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void residual_kernel(ResArgs
   const T vmax = T(D.vmax), amax = T(D.amax);
   const T pi = T(3.14159265358979323846);
 
+  T rr[AM_MAX_CIRCLES];
+#pragma unroll
+  for (int i = 0; i < AM_MAX_CIRCLES; ++i) rr[i] = i < m ? T(D.r[i]) : T(0);
+
   // squared maxima and minima are tracked, one square root at the end
   T fc2max = 0, fcsq = 0, lvl2 = T(INFINITY), slk = 0, head = 0, bc = 0, cost = 0;
   T v2max = 0, a2max = 0;
@@ -103,25 +110,26 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void residual_kernel(ResArgs
       for (int u = 0; u < kResChunk; ++u) {
         const int j = j0 + u;
         if (j >= n) break;
-        const T a = ell[0][j], b = ell[1][j];
-        for (int i = 0; i < m; ++i) {
-          const T ri = T(D.r[i]);
+        const T a = ell[0][j], b = ell[1][j], ab = ell[2][j], a2 = a * a, b2 = b * b;
+        const T ia2 = ell[3][j], ib2 = ell[4][j];
+#pragma unroll
+        for (int i = 0; i < AM_MAX_CIRCLES; ++i) {
+          if (i >= m) break;
+          const T ri = rr[i];
           const T px = x + ri * cpsi - gx[u], py = y + ri * spsi - gy[u];   // circle centre - obstacle
           const T xt = slack ? x + ri * c - gx[u] : px, yt = slack ? y + ri * s - gy[u] : py;
           T fx, fy;
           if (!literal) {
             // elliptic angle: (a d cos al, b d sin al) = (xt, yt) max(1, ab/r),
             // r = |(b xt, a yt)| (eqs. zeta_2, compute_zeta_3); al = 0, d = 1
-            // at the zero vector
-            const T r2 = b * b * xt * xt + a * a * yt * yt;
-            if (r2 > T(0)) {
-              const T g = fmax(T(1), ell[2][j] * Num<T>::rsqrt(r2));
-              fx = px - xt * g;
-              fy = py - yt * g;
-            } else {
-              fx = px - a;
-              fy = py;
-            }
+            // at the zero vector.  A centre offset whose r^2 is zero or below
+            // the smallest normal number (|offset| ~ 1e-19 m in FP32) counts
+            // as the zero vector: the hardware 1/sqrt is not defined there.
+            const T r2 = b2 * xt * xt + a2 * yt * yt;
+            const T g = fmax(T(1), ab * Num<T>::rsqrt_fast(r2));
+            const bool zero = !(r2 >= kMinNormal<T>);
+            fx = zero ? px - a : px - xt * g;
+            fy = zero ? py : py - yt * g;
           } else {
             const T al = atan2z(yt, xt);
             T sa, ca;
@@ -133,7 +141,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void residual_kernel(ResArgs
           const T f2 = fx * fx + fy * fy;
           fc2max = fmax(fc2max, f2);
           fcsq += f2;
-          lvl2 = fmin(lvl2, px * px * ell[3][j] + py * py * ell[4][j]);
+          lvl2 = fmin(lvl2, px * px * ia2 + py * py * ib2);
         }
       }
     }
