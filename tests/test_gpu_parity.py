@@ -241,6 +241,29 @@ def test_residuals_match_oracle():
     np.testing.assert_allclose(res, ref, atol=1e-7, rtol=1e-6)
 
 
+def test_f32_residuals_full_c2_match_f64_residuals_of_the_same_state():
+    """The FP32 residual kernel at the benchmark's size (B = 1000 after 100
+    iterations) against the FP64 residual kernel, which the tests above pin
+    to the oracle, evaluated on the same coefficients: the two differ only by
+    the FP32 rounding of the evaluation and of the closed forms.  Positions
+    are O(10 m) and every statistic is a distance, a speed, a heading or a
+    sum of squares of them, so 2e-4 absolute plus 1e-4 relative holds for
+    well over a thousand ulps of the largest operand."""
+    from paper_2109_13030_amd import am
+    pb, init = inputs.workload("c2")
+    h, p, st = H.run_gpu(pb, init, 100, "f32")
+    r32 = am.residuals(h, p, st).cpu().numpy()
+    out = st.numpy()
+    same = {k: out[k] for k in am.DeviceState.KEYS}
+    h64 = am.Handle.for_problem(pb, "f64")
+    p64 = am.DeviceProblem(pb, "f64")
+    st64 = am.DeviceState(same, len(pb["r"]), len(pb["oa"]), pb["q"], dtype="f64")
+    r64 = am.residuals(h64, p64, st64).cpu().numpy()
+    assert r32.shape == (1000, len(am.RES_NAMES))
+    for j, name in enumerate(am.RES_NAMES):
+        np.testing.assert_allclose(r32[:, j], r64[:, j], atol=2e-4, rtol=1e-4, err_msg=name)
+
+
 def _odd_horizon_problem(q, B=5):
     import dataclasses
     cfg = dataclasses.replace(inputs.CONFIGS["c2"], q=q)
