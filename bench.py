@@ -466,6 +466,35 @@ def error_vs_oracle(pb, gpu: dict, orc_state: dict):
             "within_1e-3": int((e <= 1e-3).sum())}
 
 
+def copy_by_size(launches=200):
+    """Bandwidth of a plain elementwise copy (half the bytes read, half
+    written) for the byte counts one launch of the plain path's elementwise
+    kernels moves (their algorithmic bytes at c2 and c4), launched back to
+    back like the plain path's kernels: what an elementwise launch of that
+    size reaches on this GPU."""
+    import torch
+    out = []
+    for label, moved in (("c2 k_targets", 30.0e6), ("c2 k_project", 44.8e6),
+                         ("c4 k_targets", 204.8e6), ("c4 k_project", 347.4e6)):
+        n = int(moved / 8)
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.mul(x, 1.0, out=y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(launches):
+            torch.mul(x, 1.0, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / launches * 1e3
+        out.append({"size_of": label, "bytes_moved": 8 * n, "us_per_launch": us,
+                    "TBps": 8 * n / (us * 1e-6) / 1e12})
+        print(f"copy {label}: {us:.2f} us, {out[-1]['TBps']:.2f} TB/s", file=sys.stderr, flush=True)
+        del x, y
+    return {"copy_by_size": out, "launches_each": launches}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -493,6 +522,9 @@ def main():
     ap.add_argument("--copy-ref", action="store_true",
                     help="run only a 512 MiB elementwise copy (y = x * 1), the size reference for "
                          "hardware byte counters, and exit")
+    ap.add_argument("--copy-sizes", action="store_true",
+                    help="run only elementwise copies (y = x * 1) that move as many bytes as one launch of "
+                         "the plain path's projection and target kernels at c2 and c4, and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -513,6 +545,9 @@ def main():
         ms = e0.elapsed_time(e1) / 2
         print(json.dumps({"copy_ref_bytes_read": x.numel() * 4, "copy_ref_bytes_written": y.numel() * 4,
                           "launches": 3, "copy_ms": ms, "copy_GBps": 2 * x.numel() * 4 / (ms * 1e-3) / 1e9}))
+        return
+    if args.copy_sizes:
+        print(json.dumps(copy_by_size()), flush=True)
         return
     if args.uneven:
         print(json.dumps(run_uneven()), flush=True)
