@@ -168,14 +168,17 @@ const char *am_last_error(void);
  * AM_XTILDE_SLACK), then `iters` iterations of xi1, xi2, xi3, xi4 and the
  * multiplier update.  With iters = 0 only the initial projection runs.
  * The state is read and written on the device; nothing is allocated.
- * batch >= 0 (0 launches nothing), iters >= 0. */
+ * batch >= 0 (0 launches nothing and reads neither st nor its arrays, which
+ * may then be NULL), iters >= 0. */
 int am_solve_batch(am_handle *h, const am_problem *p, int32_t batch, int32_t iters,
                    const am_state *st, void *stream);
 
 /* Same result as am_solve_batch computed the plain way: one kernel launch
  * per sub-step per iteration, with alpha, d and the trajectories held in
  * device memory between launches as in the paper's formulation.  Needs a
- * caller-owned device workspace of am_plain_workspace_size() bytes. */
+ * caller-owned device workspace of am_plain_workspace_size() bytes.  As
+ * for am_solve_batch, batch 0 launches nothing and reads neither st nor the
+ * workspace. */
 int am_plain_workspace_size(const am_handle *h, int32_t batch, size_t *bytes);
 int am_solve_batch_plain(am_handle *h, const am_problem *p, int32_t batch, int32_t iters,
                          const am_state *st, void *workspace, size_t workspace_bytes,
@@ -186,7 +189,8 @@ int am_solve_batch_plain(am_handle *h, const am_problem *p, int32_t batch, int32
  * q and nv.  The launch needs a caller-owned device workspace of
  * am_multi_workspace_size(nprob) bytes for the problem table.
  * handles[nprob], problems[nprob], batch[nprob], iters[nprob], states[nprob]
- * are host arrays. */
+ * are host arrays.  A problem with batch 0 gets no block and its state's
+ * arrays may be NULL. */
 int am_multi_workspace_size(int32_t nprob, size_t *bytes);
 int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *problems,
                    const int32_t *batch, const int32_t *iters, const am_state *states,
@@ -224,7 +228,8 @@ int am_autotune_multi(int32_t nprob, am_handle *const *handles, const am_problem
 /* Residual statistics of the current state (AM_RES_* columns), written to
  * device out[batch][AM_NRES] in the handle's dtype.  alpha and d are the
  * closed-form projection of the current trajectories (what the last
- * iteration left).  Reads cx, cc, cy, cs, cpsi, lam, lam_psi of st. */
+ * iteration left).  Reads cx, cc, cy, cs, cpsi, lam, lam_psi of st.
+ * batch 0 launches nothing (st and out may then hold NULL arrays). */
 int am_residuals(am_handle *h, const am_problem *p, int32_t batch, const am_state *st,
                  void *out, void *stream);
 
@@ -234,7 +239,7 @@ int am_residuals(am_handle *h, const am_problem *p, int32_t batch, const am_stat
  * among trajectories with no non-finite value and max |f_c| <= fc_tol
  * (metres), the least AM_RES_COST; if none qualifies, the least max |f_c|;
  * ties go to the lower index.  Writes the index (-1 if every trajectory is
- * non-finite) to device int32 *best and, when values is not NULL, (cost,
+ * non-finite, or batch is 0) to device int32 *best and, when values is not NULL, (cost,
  * max |f_c|) of that trajectory to device values[2] (handle's dtype).
  * Stream-ordered, asynchronous. */
 int am_select_best(const am_handle *h, int32_t batch, const void *residuals, double fc_tol, int32_t *best,

@@ -296,9 +296,9 @@ int am_solve_batch(am_handle *h, const am_problem *p, int32_t batch, int32_t ite
   if (batch < 0 || iters < 0) return fail(AM_ERR_INVALID, "batch and iters must be >= 0");
   int rc;
   if ((rc = check_problem(h, p)) != AM_OK) return rc;
-  if ((rc = check_state(st)) != AM_OK) return rc;
   if ((rc = check_device(h)) != AM_OK) return rc;
-  if (batch == 0) return AM_OK;
+  if (batch == 0) return AM_OK;   // empty arrays may come as NULL
+  if ((rc = check_state(st)) != AM_OK) return rc;
   const Desc d = make_desc(h, p, batch, iters, st, h->tile);
   const size_t lds = amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64, h->tile, h->waves);
   if (lds > lds_limit())
@@ -343,7 +343,7 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
     if (batch[k] < 0 || iters[k] < 0) return fail(AM_ERR_INVALID, "problem %d: negative batch or iters", k);
     int rc;
     if ((rc = check_problem(h, &problems[k])) != AM_OK) return rc;
-    if ((rc = check_state(&states[k])) != AM_OK) return rc;
+    if (batch[k] > 0 && (rc = check_state(&states[k])) != AM_OK) return rc;
     if ((rc = check_device(h)) != AM_OK) return rc;
     Desc d = make_desc(h, &problems[k], batch[k], iters[k], &states[k], h0->tile);
     d.blk0 = blocks;
@@ -370,8 +370,9 @@ int am_residuals(am_handle *h, const am_problem *p, int32_t batch, const am_stat
   if (!out && batch > 0) return fail(AM_ERR_INVALID, "out is NULL");
   int rc;
   if ((rc = check_problem(h, p)) != AM_OK) return rc;
-  if ((rc = check_state(st)) != AM_OK) return rc;
   if ((rc = check_device(h)) != AM_OK) return rc;
+  if (batch == 0) return AM_OK;   // empty arrays may come as NULL
+  if ((rc = check_state(st)) != AM_OK) return rc;
   const Desc d = make_desc(h, p, batch, 0, st, h->tile);
   hipError_t e = amk::launch_residuals(d, h->c.tP, h->c.tPd, h->c.tPdd, out, h->f64, h->shape.nv,
                                        static_cast<hipStream_t>(stream));
@@ -484,9 +485,9 @@ int am_solve_batch_plain(am_handle *h, const am_problem *p, int32_t batch, int32
   if (batch < 0 || iters < 0) return fail(AM_ERR_INVALID, "batch and iters must be >= 0");
   int rc;
   if ((rc = check_problem(h, p)) != AM_OK) return rc;
-  if ((rc = check_state(st)) != AM_OK) return rc;
   if ((rc = check_device(h)) != AM_OK) return rc;
-  if (batch == 0) return AM_OK;
+  if (batch == 0) return AM_OK;   // empty arrays may come as NULL
+  if ((rc = check_state(st)) != AM_OK) return rc;
   const size_t need = amk::plain_workspace_bytes(batch, h->shape.q, h->shape.nv, h->shape.m, h->shape.n_obs, h->f64);
   if (!workspace || workspace_bytes < need)
     return fail(AM_ERR_INVALID, "workspace of %zu bytes needed", need);

@@ -313,6 +313,40 @@ def test_multi_problem_launch_equals_single_launches():
             assert torch.equal(s.t[k], s1.t[k]), k
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_empty_batches_launch_nothing(dtype):
+    """Batch 0 with empty (NULL) arrays: every entry point succeeds and
+    launches nothing; the selection reports -1; an empty problem between two
+    others in one multi-problem launch leaves their results as in single
+    launches."""
+    import torch
+    from paper_2109_13030_amd import am
+    pb, init = inputs.workload("c1", batch=3)
+    m, n, q = len(pb["r"]), len(pb["oa"]), pb["q"]
+    empty = {k: np.zeros((0,) + np.asarray(v).shape[1:]) for k, v in init.items()}
+    h = am.Handle.for_problem(pb, dtype)
+    p = am.DeviceProblem(pb, dtype)
+    st = am.DeviceState(empty, m, n, q, dtype=dtype)
+    for k in st.t:
+        st.t[k] = None   # every array pointer NULL
+    am.solve(h, p, st, 5)
+    am.solve_plain(h, p, st, 5, torch.empty(0, dtype=torch.uint8, device="cuda"))
+    res = am.residuals(h, p, st, out=torch.empty((0, am.NRES), dtype=torch.float32 if dtype == "f32"
+                                                 else torch.float64, device="cuda"))
+    assert tuple(res.shape) == (0, am.NRES)
+    assert am.select_best(h, res, 0.05) == (-1, 0.0, 0.0)
+    a = am.DeviceState(init, m, n, q, dtype=dtype)
+    b = am.DeviceState(init, m, n, q, dtype=dtype)
+    ws = torch.empty(am.multi_workspace_size(3), dtype=torch.uint8, device="cuda")
+    am.solve_multi([h, h, h], [p, p, p], [a, st, b], 7, ws)
+    one = am.DeviceState(init, m, n, q, dtype=dtype)
+    am.solve(h, p, one, 7)
+    torch.cuda.synchronize()
+    for k in ("cx", "cy", "cpsi", "lam", "lam_psi", "traj"):
+        assert torch.equal(a.t[k], one.t[k]), k
+        assert torch.equal(b.t[k], one.t[k]), k
+
+
 # ------------------------------------------------------------- plain path (one launch per sub-step)
 
 def test_plain_f64_matches_oracle():
