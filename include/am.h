@@ -176,8 +176,12 @@ int am_solve_batch(am_handle *h, const am_problem *p, int32_t batch, int32_t ite
 /* Same result as am_solve_batch computed the plain way: one kernel launch
  * per sub-step per iteration, with alpha, d and the trajectories held in
  * device memory between launches as in the paper's formulation.  Needs a
- * caller-owned device workspace of am_plain_workspace_size() bytes.  As
- * for am_solve_batch, batch 0 launches nothing and reads neither st nor the
+ * caller-owned device workspace of am_plain_workspace_size() bytes, 16-byte
+ * aligned (AM_ERR_INVALID otherwise; any hipMalloc allocation is).  Its
+ * kernels read the obstacle rows and write alpha, d two or four time steps
+ * at a time when q is even, so obs_x and obs_y should then be 16-byte
+ * aligned too (any other alignment is slower, not wrong).  As for
+ * am_solve_batch, batch 0 launches nothing and reads neither st nor the
  * workspace. */
 int am_plain_workspace_size(const am_handle *h, int32_t batch, size_t *bytes);
 int am_solve_batch_plain(am_handle *h, const am_problem *p, int32_t batch, int32_t iters,

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -491,6 +492,8 @@ int am_solve_batch_plain(am_handle *h, const am_problem *p, int32_t batch, int32
   const size_t need = amk::plain_workspace_bytes(batch, h->shape.q, h->shape.nv, h->shape.m, h->shape.n_obs, h->f64);
   if (!workspace || workspace_bytes < need)
     return fail(AM_ERR_INVALID, "workspace of %zu bytes needed", need);
+  if (reinterpret_cast<uintptr_t>(workspace) % 16 != 0)
+    return fail(AM_ERR_INVALID, "workspace must be 16-byte aligned");
   const Desc d = make_desc(h, p, batch, iters, st, h->tile);
   hipError_t e = amk::launch_plain(d, workspace, workspace_bytes, h->f64, h->shape.nv,
                                    static_cast<hipStream_t>(stream));

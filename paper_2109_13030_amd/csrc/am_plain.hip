@@ -198,18 +198,35 @@ __global__ void k_xi2(Desc D, Ptrs<T> w) {
 constexpr int kItemThreads = 512;
 inline int item_threads(int items) { return std::min(kItemThreads, (items + 63) / 64 * 64); }
 
-// ---- xi3/xi4: alpha_ij, d_ij for every (l, i, j, t); items m q .. (m + 1) q - 1
-// are the velocity/acceleration pairs alpha_v, d_v, alpha_a, d_a at t = k - m q.
-// The items of all trajectories form one flat range over small blocks, so
-// the last blocks of a launch are short.
-// rows per chunk of loads (half for FP64, whose values take two registers)
-template <typename T> constexpr int kProjChunk = sizeof(T) == 4 ? 8 : 4;
+// V consecutive values of a row as one aligned load or store
+template <typename T, int V>
+struct alignas(V * sizeof(T)) Vec {
+  T v[V];
+};
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> ldv(const T *p) {
+  return *reinterpret_cast<const Vec<T, V> *>(p);
+}
+template <typename T, int V>
+__device__ __forceinline__ void stv(T *p, const Vec<T, V> &x) {
+  *reinterpret_cast<Vec<T, V> *>(p) = x;
+}
 
-template <typename T>
+// ---- xi3/xi4: alpha_ij, d_ij for every (l, i, j, t); items (i, t) with
+// i = m are the velocity/acceleration pairs alpha_v, d_v, alpha_a, d_a.
+// An item covers V consecutive time steps (V = 2 when q is even: aligned
+// 8- or 16-byte loads and stores, and half the wavefronts, so that one round
+// of them fills the GPU).  The items of all trajectories form one flat range
+// over small blocks, so the last blocks of a launch are short.
+// rows per chunk of loads (fewer for FP64 and for two steps per item)
+template <typename T, int V> constexpr int kProjChunk = (sizeof(T) == 4 ? 8 : 4) / V;
+
+template <typename T, int V>
 __global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
   __shared__ T ell[4][AM_MAX_OBS];  // a_j, b_j (grown by the circle radius), 1/a_j^2, 1/b_j^2
   const int q = D.q, m = D.m, n = D.n;
-  const int per = (m + 1) * q;
+  const int qv = q / V;   // items per row; V divides q
+  const int per = (m + 1) * qv;
   const int g = int(blockIdx.x) * kThreads + int(threadIdx.x);
   const bool slack = D.flags & AM_XTILDE_SLACK, literal = D.flags & AM_ALPHA_LITERAL;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -222,63 +239,90 @@ __global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
   __syncthreads();
   if (g >= D.B * per) return;
   const int l = g / per, k = g - l * per;
+  const int i = k / qv, t = (k - i * qv) * V;
   const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
-  const T *ox = static_cast<const T *>(D.ox), *oy = static_cast<const T *>(D.oy);
   const T offx = T(D.offx), offy = T(D.offy);
-  {
-    const int i = k / q, t = k - i * q;
-    if (i < m) {
-      const T ri = T(D.r[i]);
-      const T ux = slack ? tr[3 * q + t] : p3[q + t], uy = slack ? tr[7 * q + t] : p3[2 * q + t];
-      const T px = tr[t] + ri * ux, py = tr[4 * q + t] + ri * uy;
-      const size_t row0 = (size_t(l) * m + i) * n;
-      T *oal = w.alpha + row0 * q + t, *od = w.d + row0 * q + t;
-      const T *oxt = ox + t, *oyt = oy + t;
-      // obstacle positions are loaded a chunk at a time, so one memory
-      // latency covers a chunk of outputs
-      for (int j0 = 0; j0 < n; j0 += kProjChunk<T>) {
-        T gx[kProjChunk<T>], gy[kProjChunk<T>];
+  if (i < m) {
+    const T ri = T(D.r[i]);
+    const Vec<T, V> xv = ldv<T, V>(tr + t), yv = ldv<T, V>(tr + 4 * q + t);
+    const Vec<T, V> uxv = slack ? ldv<T, V>(tr + 3 * q + t) : ldv<T, V>(p3 + q + t);
+    const Vec<T, V> uyv = slack ? ldv<T, V>(tr + 7 * q + t) : ldv<T, V>(p3 + 2 * q + t);
+    T px[V], py[V];
 #pragma unroll
-        for (int u = 0; u < kProjChunk<T>; ++u) {
-          const int j = j0 + u < n ? j0 + u : n - 1;
-          gx[u] = oxt[j * q];
-          gy[u] = oyt[j * q];
-        }
+    for (int e = 0; e < V; ++e) {
+      px[e] = xv.v[e] + ri * uxv.v[e];
+      py[e] = yv.v[e] + ri * uyv.v[e];
+    }
+    const size_t row0 = (size_t(l) * m + i) * n;
+    T *oal = w.alpha + row0 * q + t, *od = w.d + row0 * q + t;
+    const T *oxt = static_cast<const T *>(D.ox) + t, *oyt = static_cast<const T *>(D.oy) + t;
+    // obstacle positions are loaded a chunk at a time, so one memory
+    // latency covers a chunk of outputs
+    constexpr int CH = kProjChunk<T, V>;
+    for (int j0 = 0; j0 < n; j0 += CH) {
+      Vec<T, V> gx[CH], gy[CH];
 #pragma unroll
-        for (int u = 0; u < kProjChunk<T>; ++u) {
-          const int j = j0 + u;
-          if (j >= n) break;
-          const T a = ell[0][j], b = ell[1][j];
-          const T xt = px - (gx[u] - offx), yt = py - (gy[u] - offy);
-          T al, dd;
+      for (int u = 0; u < CH; ++u) {
+        const int j = j0 + u < n ? j0 + u : n - 1;
+        gx[u] = ldv<T, V>(oxt + size_t(j) * q);
+        gy[u] = ldv<T, V>(oyt + size_t(j) * q);
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int j = j0 + u;
+        if (j >= n) break;
+        const T a = ell[0][j], b = ell[1][j], ia2 = ell[2][j], ib2 = ell[3][j];
+        Vec<T, V> al, dd;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const T xt = px[e] - (gx[u].v[e] - offx), yt = py[e] - (gy[u].v[e] - offy);
           if (!literal) {
             // elliptic angle: the point (a d cos al, b d sin al) is (xt, yt)
             // itself, so d = sqrt(xt^2/a^2 + yt^2/b^2) (eq. compute_zeta_3)
-            al = atan2z(a * yt, b * xt);
-            dd = fmax(T(1), Num<T>::sqrt_fast(xt * xt * ell[2][j] + yt * yt * ell[3][j]));
+            al.v[e] = atan2z(a * yt, b * xt);
+            dd.v[e] = fmax(T(1), Num<T>::sqrt_fast(xt * xt * ia2 + yt * yt * ib2));
           } else {
-            al = atan2z(yt, xt);
+            al.v[e] = atan2z(yt, xt);
             T sa, ca;
-            Num<T>::sincos_(al, &sa, &ca);
-            dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
+            Num<T>::sincos_(al.v[e], &sa, &ca);
+            dd.v[e] = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
           }
-          oal[size_t(j) * q] = al;
-          od[size_t(j) * q] = dd;
         }
+        stv<T, V>(oal + size_t(j) * q, al);
+        stv<T, V>(od + size_t(j) * q, dd);
       }
-    } else {
-      const T xd = tr[q + t], yd = tr[5 * q + t], xdd = tr[2 * q + t], ydd = tr[6 * q + t];
-      const T av = atan2z(yd, xd), aa = atan2z(ydd, xdd);
-      T sv, cv, sa, ca;
-      Num<T>::sincos_(av, &sv, &cv);
-      Num<T>::sincos_(aa, &sa, &ca);
-      T *o = w.va4 + size_t(l) * 4 * q;
-      o[t] = av;
-      o[q + t] = fmin(T(1), fmax(T(0), (xd * cv + yd * sv) / T(D.vmax)));
-      o[2 * q + t] = aa;
-      o[3 * q + t] = fmin(T(1), fmax(T(0), (xdd * ca + ydd * sa) / T(D.amax)));
     }
+  } else {
+    T *o = w.va4 + size_t(l) * 4 * q;
+    const Vec<T, V> xdv = ldv<T, V>(tr + q + t), ydv = ldv<T, V>(tr + 5 * q + t);
+    const Vec<T, V> xddv = ldv<T, V>(tr + 2 * q + t), yddv = ldv<T, V>(tr + 6 * q + t);
+    Vec<T, V> av, dv, aa, da;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const T xd = xdv.v[e], yd = ydv.v[e], xdd = xddv.v[e], ydd = yddv.v[e];
+      av.v[e] = atan2z(yd, xd);
+      aa.v[e] = atan2z(ydd, xdd);
+      T sv, cv, sa, ca;
+      Num<T>::sincos_(av.v[e], &sv, &cv);
+      Num<T>::sincos_(aa.v[e], &sa, &ca);
+      dv.v[e] = fmin(T(1), fmax(T(0), (xd * cv + yd * sv) / T(D.vmax)));
+      da.v[e] = fmin(T(1), fmax(T(0), (xdd * ca + ydd * sa) / T(D.amax)));
+    }
+    stv<T, V>(o + t, av);
+    stv<T, V>(o + q + t, dv);
+    stv<T, V>(o + 2 * q + t, aa);
+    stv<T, V>(o + 3 * q + t, da);
   }
+}
+
+// Projection launch: two time steps per item when q is even.
+template <typename T>
+void project(const Desc &D, const Ptrs<T> &w, hipStream_t st) {
+  const size_t rows = size_t(D.B) * (D.m + 1);
+  if (D.q % 2 == 0)
+    hipLaunchKernelGGL((k_project<T, 2>), dim3(blocks_for(rows * (D.q / 2))), dim3(kThreads), 0, st, D, w);
+  else
+    hipLaunchKernelGGL((k_project<T, 1>), dim3(blocks_for(rows * D.q)), dim3(kThreads), 0, st, D, w);
 }
 
 // ---- residual channels of F xi - g per (l, t), reading alpha and d.  Item
@@ -286,15 +330,6 @@ __global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
 // of a t meet in LDS and one thread per t forms the channels.
 template <typename T> constexpr int kTgtChunk = sizeof(T) == 4 ? 8 : 4;  // d_ij loads issued together
 
-// V consecutive values of a row as one aligned load
-template <typename T, int V>
-struct alignas(V * sizeof(T)) Vec {
-  T v[V];
-};
-template <typename T, int V>
-__device__ __forceinline__ Vec<T, V> ldv(const T *p) {
-  return *reinterpret_cast<const Vec<T, V> *>(p);
-}
 
 template <typename T, int V>
 __global__ __launch_bounds__(kItemThreads) void k_targets(Desc D, Ptrs<T> w) {
@@ -703,14 +738,14 @@ hipError_t run(const Desc &D, void *ws, hipStream_t st) {
   // step 1: initial xi3, xi4 from the given trajectories
   hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
   hipLaunchKernelGGL((k_eval_psi<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
-  hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(size_t(B) * (D.m + 1) * q)), dim3(kThreads), 0, st, D, w);
+  project<T>(D, w, st);
   targets<T>(D, w, st);
   contract<T, NV>(D, w, st, 0);
   for (int it = 0; it < D.K; ++it) {
     xi1<T, NV>(D, w, st);
     hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_xi2<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w);
-    hipLaunchKernelGGL((k_project<T>), dim3(blocks_for(size_t(B) * (D.m + 1) * q)), dim3(kThreads), 0, st, D, w);
+    project<T>(D, w, st);
     targets<T>(D, w, st);
     contract<T, NV>(D, w, st, 1);
   }
