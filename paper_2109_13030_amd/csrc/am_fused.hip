@@ -501,11 +501,15 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       pr[3 * NV + k] = Ub[k] * ro2y;
       pr[4 * NV + k] = Ut[k] * rp;
     }
+    // the reduction and exchange are the pair's critical path: while a wave
+    // is in them the SIMD issues its instructions first
+    __builtin_amdgcn_s_setprio(2);
     const T tot = wave_sum_many<T, G, RED>(pr, red, lane);
     if (lane < G) xmine[lane] = tot;
     __syncthreads();
     if (prow) tr = exchange_sum(lane);
     if (hrow) trpsi = exchange_sum(4 * NV + lane);
+    __builtin_amdgcn_s_setprio(0);
   };
 
   // ---- step 1 of the AM list: initial xi3, xi4 from the given trajectory
@@ -553,10 +557,12 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     T pp[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) pp[k] = Ut[k] * psih;
+    __builtin_amdgcn_s_setprio(2);
     const T upsi = wave_sum_many<T, NV, RED>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = upsi;
     __syncthreads();
     if (hrow) vzpsi[lane] = hpsi + mu + rho * exchange_sum(kXchBig + lane);
+    __builtin_amdgcn_s_setprio(0);
     wave_sync();
     eval_psi();
 
