@@ -87,7 +87,7 @@ Desc make_desc(const am_handle *h, const am_problem *p, int32_t batch, int32_t i
   std::memset(&d, 0, sizeof d);
   const Consts &c = h->c;
   d.U = c.tU; d.V = c.tV; d.W = c.tW; d.M1 = c.tM1; d.H1 = c.tH1; d.M2 = c.tM2; d.H2 = c.tH2;
-  d.GF = c.tGF; d.Ut = c.tUt; d.R = c.R; d.Rinv = c.Rinv;
+  d.GF = c.tGF; d.N = c.tN; d.Ut = c.tUt; d.R = c.R; d.Rinv = c.Rinv; d.Ud = c.U; d.Abc = c.Abc; d.H1d = c.H1;
   d.ox = p->obs_x; d.oy = p->obs_y; d.oa = p->obs_a; d.ob = p->obs_b;
   d.cx = st->cx; d.cc = st->cc; d.cy = st->cy; d.cs = st->cs; d.cpsi = st->cpsi;
   d.lam = st->lam; d.lampsi = st->lam_psi;
@@ -223,7 +223,8 @@ int am_setup(const am_shape *s, am_handle **out) {
                     size_t(nv * nv), size_t(nv * nv), size_t(3 * nv * nv),
                     size_t(N1 * N1), size_t(N2 * N2), size_t(2 * N1 * N1), size_t(2 * N2 * N2),
                     size_t(n2 * n2), size_t(n2 * 6), size_t(nv * nv), size_t(nv * 6), size_t(n2 * n2),
-                    size_t(N1 * N1), size_t(N2 * N2), 8, size_t(AM_MAX_CIRCLES), size_t(q * nv)};
+                    size_t(N1 * N1), size_t(N2 * N2), 8, size_t(AM_MAX_CIRCLES), size_t(q * nv),
+                    size_t(n2 * n2), size_t(6 * nv)};
   const int nparts = int(sizeof(sizes) / sizeof(sizes[0]));
   size_t off[32], tot = 0;
   for (int i = 0; i < nparts; ++i) { off[i] = tot; tot += align_up(sizes[i], 32); }
@@ -238,12 +239,14 @@ int am_setup(const am_shape *s, am_handle **out) {
   c.K2b_inv = b + off[19]; c.status = b + off[20];
   double *r_dev = b + off[21];
   c.Ut = b + off[22];
+  c.N = b + off[23];
+  c.Abc = b + off[24];
 
   // typed carve-up (in elements)
   const size_t es = h->f64 ? 8 : 4;
   size_t tsz[] = {size_t(q * nv), size_t(q * nv), size_t(q * nv), size_t(n2 * n2), size_t(n2 * 6),
                   size_t(nv * nv), size_t(nv * 6), size_t(n2 * n2), size_t(q * nv), size_t(q * nv),
-                  size_t(q * nv), size_t(q * nv)};
+                  size_t(q * nv), size_t(q * nv), size_t(n2 * n2)};
   constexpr int ntyped = int(sizeof(tsz) / sizeof(tsz[0]));
   size_t toff[16], ttot = 0;
   for (int i = 0; i < ntyped; ++i) { toff[i] = ttot; ttot += align_up(tsz[i], 64); }
@@ -254,7 +257,7 @@ int am_setup(const am_shape *s, am_handle **out) {
     return fail(AM_ERR_NOMEM, "hipMalloc of %zu bytes failed", ttot * es);
   }
   char *tb = static_cast<char *>(h->bufT);
-  void **tp[] = {&c.tU, &c.tV, &c.tW, &c.tM1, &c.tH1, &c.tM2, &c.tH2, &c.tGF, &c.tP, &c.tPd, &c.tPdd, &c.tUt};
+  void **tp[] = {&c.tU, &c.tV, &c.tW, &c.tM1, &c.tH1, &c.tM2, &c.tH2, &c.tGF, &c.tP, &c.tPd, &c.tPdd, &c.tUt, &c.tN};
   static_assert(sizeof(tp) / sizeof(tp[0]) == ntyped, "typed buffers");
   for (int i = 0; i < ntyped; ++i) *tp[i] = tb + toff[i] * es;
 

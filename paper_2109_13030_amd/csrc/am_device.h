@@ -135,45 +135,52 @@ struct alignas(4 * sizeof(T)) Quad {
 };
 
 // LDS carve-up of the fused kernel, in elements of T.  Offsets are multiples
-// of 4 elements, so Pair and Quad reads are aligned.
+// of 8 elements, so Pair and Quad reads (and FP64 pairs when T is float)
+// are aligned.
 struct FusedLds {
-  int oxy;                 // centred obstacle centres, Pair [n][q]
+  int oxy;                 // obstacle centres, Pair [n][q]
   int op;                  // per-obstacle parameters [n][8] (OP_*)
-  int m1, gf;              // [2nv][2nv] operators as Quad [a2/4][2nv]
+  int m1, gf;              // [2nv][2nv] operators M1 and N as Quad [a2/4][2nv]
   int xch;                 // [traj][half][kXchHalf] exchange area
   int wave0, wave_stride;  // per-wave areas
   int total;
 };
 
 // Per-wave vectors.  Position-block vectors hold one axis in 2nv contiguous
-// entries (x block then slack block), padded to a2 = pad4(2nv).
+// entries (x block then slack block), padded to a2 = pad4(2nv).  The
+// coefficients and the right-hand sides of the coefficient update are kept
+// in FP64 (zd, wd; dw elements of T per double), with a T copy of the
+// coefficients (z) for the evaluation of the derivative channels.
 struct WaveLds {
-  int z, rhs, zpsi, aux, red;
+  int z, zd, wd, zpsi, aux, red;
 };
 
-__host__ __device__ inline WaveLds wave_layout(int nv, int red_rows) {
+__host__ __device__ constexpr int pad8(int v) { return (v + 7) & ~7; }
+
+__host__ __device__ inline WaveLds wave_layout(int nv, int red_rows, int dw) {
   const int p = pad4(nv), a2 = pad4(2 * nv);
   WaveLds w;
   int o = 0;
-  w.z = o; o += 2 * a2;         // z of (x, c) and (y, s)
-  w.rhs = o; o += 2 * a2;       // lambda + rho F^T g
-  w.zpsi = o; o += p;           // heading coefficients
-  w.aux = o; o += 2 * a2 + p;   // set-up and write-back staging
+  w.z = o; o += pad8(2 * a2);           // T copy of z of (x, c) and (y, s)
+  w.zd = o; o += pad8(2 * a2 * dw);     // z in FP64
+  w.wd = o; o += pad8(2 * a2 * dw);     // lambda - rho F^T (F xi - g) in FP64
+  w.zpsi = o; o += pad8(p);             // heading coefficients
+  w.aux = o; o += pad8(2 * a2 + p);     // set-up staging
   w.red = o; o += red_rows * kRedRowStride;
   return w;
 }
 
-__host__ __device__ inline FusedLds fused_layout(int q, int n, int nv, int tile, int red_rows) {
+__host__ __device__ inline FusedLds fused_layout(int q, int n, int nv, int tile, int red_rows, int dw) {
   FusedLds L;
   const int a2 = pad4(2 * nv);
   int o = 0;
-  L.oxy = o; o += pad4(2 * n * q);
+  L.oxy = o; o += pad8(2 * n * q);
   L.op = o; o += 8 * n;
   L.m1 = o; o += a2 * 2 * nv;
   L.gf = o; o += a2 * 2 * nv;
   L.xch = o; o += tile * 2 * kXchHalf;
-  const WaveLds w = wave_layout(nv, red_rows);
-  L.wave_stride = pad4(w.red + red_rows * kRedRowStride);
+  const WaveLds w = wave_layout(nv, red_rows, dw);
+  L.wave_stride = pad8(w.red + red_rows * kRedRowStride);
   L.wave0 = o; o += 2 * tile * L.wave_stride;
   L.total = o;
   return L;

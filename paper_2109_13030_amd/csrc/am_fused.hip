@@ -24,9 +24,19 @@
 //    ellipse, so obstacles farther from the robot centre than the farthest
 //    circle plus the larger semi-axis are skipped (a wave-wide vote per
 //    obstacle).
-//  * lambda <- lambda - rho F^T (F xi - g) (eq. update_lambda_1) and the next
-//    right-hand side lambda + rho F^T g = lambda + rho (F^T F xi - F^T(F xi - g))
-//    share the single reduction F^T (F xi - g).
+//  * lambda <- lambda - rho F^T (F xi - g) (eq. update_lambda_1) and the
+//    next xi1 right-hand side lambda + rho F^T g share the single reduction
+//    F^T (F xi - g).
+//  * The xi1 step is applied as an update of the current coefficients.  With
+//    [M1 H1] the first block row of the KKT inverse (eq. over_3), the identity
+//    M1 (Q + rho F^T F) + H1 A = I turns z' = H1 b + M1 (lambda + rho F^T g)
+//    into z' = z - H1 (A z - b) + M1 (lambda - rho F^T (F xi - g)) - N z with
+//    N = M1 Q.  Every term on the right but z is small once the iteration
+//    settles, so the FP32 rounding of the operators and of the large product
+//    F^T F z no longer enters z; z, the multipliers and the update itself are
+//    carried in FP64, and so are the positions x = U z and their offsets
+//    from the obstacle centres.  A z = b holds after the first update, so
+//    the boundary term is applied once.
 //  * The heading step (eq. compute_convex_surrogate) needs M2 (lambda_psi +
 //    rho U^T psi_hat).  The kernel carries mu = M2 lambda_psi instead of
 //    lambda_psi and reduces with the rows of U~ = U M2^T, so one reduction
@@ -35,8 +45,9 @@
 //    lambda_psi itself is linear in the summed residuals, so each lane sums
 //    psi - psi_hat over the iterations and lambda_psi is formed once at the
 //    end.
-//  * Positions are shifted by the midpoint of start and goal on entry and back
-//    on exit (exact: the basis reproduces constants, P 1 = 1, Pdot 1 = 0).
+//  * Coefficients are shifted by the midpoint of start and goal on entry and
+//    back on exit (exact: the basis reproduces constants, P 1 = 1,
+//    Pdot 1 = 0).
 #include <hip/hip_runtime.h>
 
 #include "am_device.h"
@@ -119,21 +130,23 @@ __device__ __forceinline__ T wave_sum_many(const T (&p)[G], T *red, int lane) {
   return s;
 }
 
-// Row I of a [2nv][2nv] operator stored as Quad [a2/4][2nv] times the
-// 2nv-vector v (contiguous, 16-byte aligned, padded to a2).
+// Row I of a [2nv][2nv] operator stored as Quad [a2/4][2nv] times the FP64
+// 2nv-vector v (contiguous, 16-byte aligned, padded to a2), accumulated in
+// FP64.
 template <typename T, int NV>
-__device__ __forceinline__ T row_dot(const T *op, int I, const T *v) {
+__device__ __forceinline__ double row_dot(const T *op, int I, const double *v) {
   constexpr int N2 = 2 * NV, C = pad4(N2) / 4;
   const Quad<T> *o = reinterpret_cast<const Quad<T> *>(op);
-  const Quad<T> *vv = reinterpret_cast<const Quad<T> *>(v);
-  T acc0 = T(0), acc1 = T(0);
+  const Pair<double> *vv = reinterpret_cast<const Pair<double> *>(v);
+  double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const Quad<T> a = o[c * N2 + I], b = vv[c];
-    acc0 += a.a * b.a;
-    acc1 += a.b * b.b;
-    if (4 * c + 2 < N2) acc0 += a.c * b.c;
-    if (4 * c + 3 < N2) acc1 += a.d * b.d;
+    const Quad<T> a = o[c * N2 + I];
+    const Pair<double> b0 = vv[2 * c], b1 = vv[2 * c + 1];
+    acc0 += double(a.a) * b0.x;
+    acc1 += double(a.b) * b0.y;
+    if (4 * c + 2 < N2) acc0 += double(a.c) * b1.x;
+    if (4 * c + 3 < N2) acc1 += double(a.d) * b1.y;
   }
   return acc0 + acc1;
 }
@@ -156,17 +169,17 @@ __device__ __forceinline__ void row_load(const T *op, int I, T (&r)[pad4(2 * NV)
 
 // The same product with the row in registers.
 template <typename T, int NV>
-__device__ __forceinline__ T row_dot_reg(const T (&r)[pad4(2 * NV)], const T *v) {
+__device__ __forceinline__ double row_dot_reg(const T (&r)[pad4(2 * NV)], const double *v) {
   constexpr int N2 = 2 * NV, C = pad4(N2) / 4;
-  const Quad<T> *vv = reinterpret_cast<const Quad<T> *>(v);
-  T acc0 = T(0), acc1 = T(0);
+  const Pair<double> *vv = reinterpret_cast<const Pair<double> *>(v);
+  double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const Quad<T> b = vv[c];
-    acc0 += r[4 * c] * b.a;
-    acc1 += r[4 * c + 1] * b.b;
-    if (4 * c + 2 < N2) acc0 += r[4 * c + 2] * b.c;
-    if (4 * c + 3 < N2) acc1 += r[4 * c + 3] * b.d;
+    const Pair<double> b0 = vv[2 * c], b1 = vv[2 * c + 1];
+    acc0 += double(r[4 * c]) * b0.x;
+    acc1 += double(r[4 * c + 1]) * b0.y;
+    if (4 * c + 2 < N2) acc0 += double(r[4 * c + 2]) * b1.x;
+    if (4 * c + 3 < N2) acc1 += double(r[4 * c + 3]) * b1.y;
   }
   return acc0 + acc1;
 }
@@ -176,10 +189,12 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
                            int lane, int wave) {
   constexpr int A2 = pad4(2 * NV), N2 = 2 * NV;
   constexpr int G = 5 * NV;   // rows of the per-iteration reduction
+  constexpr int DW = int(sizeof(double) / sizeof(T));   // elements of T per FP64 value
   // descriptor fields used in the loop, as locals
   const int q = uni(Dsrc.q), m = uni(Dsrc.m), n = uni(Dsrc.n), flags = uni(Dsrc.flags), K = uni(Dsrc.K);
   const T rho = uni(T(Dsrc.rho)), rhop = uni(T(Dsrc.rho_psi)), vmax = uni(T(Dsrc.vmax)),
           amax = uni(T(Dsrc.amax));
+  const double rhod = uni(Dsrc.rho);
   const double offx = uni(Dsrc.offx), offy = uni(Dsrc.offy);
   const bool slack = flags & AM_XTILDE_SLACK;
   const bool literal_alpha = flags & AM_ALPHA_LITERAL;
@@ -197,10 +212,11 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   const Pair<T> *oxy = reinterpret_cast<const Pair<T> *>(lds + L.oxy);
   const T *op = lds + L.op;
   const Quad<T> *opq = reinterpret_cast<const Quad<T> *>(lds + L.op);
-  const T *M1 = lds + L.m1, *GF = lds + L.gf;
-  const WaveLds wl = wave_layout(NV, RED);
+  const T *M1 = lds + L.m1, *NQ = lds + L.gf;
+  const WaveLds wl = wave_layout(NV, RED, DW);
   T *wb = lds + L.wave0 + wave * L.wave_stride;
-  T *vz = wb + wl.z, *vrhs = wb + wl.rhs, *vzpsi = wb + wl.zpsi, *vaux = wb + wl.aux;
+  T *vz = wb + wl.z, *vzpsi = wb + wl.zpsi, *vaux = wb + wl.aux;
+  double *vzd = reinterpret_cast<double *>(wb + wl.zd), *vwd = reinterpret_cast<double *>(wb + wl.wd);
   T *red = wb + wl.red;
   // exchange area of this trajectory: [half][kXchHalf]
   T *xch = lds + L.xch + (wave >> 1) * 2 * kXchHalf;
@@ -223,8 +239,10 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
           *gW = static_cast<const T *>(Dsrc.W), *gUt = static_cast<const T *>(Dsrc.Ut),
           *gM2 = static_cast<const T *>(Dsrc.M2);
   T Ub[NV], Vb[NV], Wb[NV], Ut[NV];
+  double Ubd[NV];   // FP64 rows for the positions
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
+    Ubd[k] = tv ? Dsrc.Ud[tt * NV + k] : 0.0;
     Ub[k] = tv ? gU[tt * NV + k] : T(0);
     Vb[k] = tv ? gV[tt * NV + k] : T(0);
     Wb[k] = tv ? gW[tt * NV + k] : T(0);
@@ -233,17 +251,11 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 
   // ---- boundary terms h = H b (centred positions) and the initial state
   const double *R = Dsrc.R, *Rinv = Dsrc.Rinv;
-  T hreg = T(0), lam = T(0), hpsi = T(0), lampsi0 = T(0);
+  // lane I of the position block: its coefficient, multiplier and the
+  // boundary correction of the first update, in FP64
+  double zl = 0.0, lam = 0.0, bcc = 0.0;
+  T hpsi = T(0), lampsi0 = T(0);
   if (prow) {
-    const double *bb = axis == 0 ? Dsrc.bx : Dsrc.by;
-    const double off = axis == 0 ? offx : offy;
-    const T *H1 = static_cast<const T *>(Dsrc.H1);
-    double hsum = 0.0;
-    for (int e = 0; e < 6; ++e) {
-      const double be = (e == 0 || e == 3) ? bb[e] - off : bb[e];
-      hsum += double(H1[I * 6 + e]) * be;
-    }
-    hreg = T(hsum);
     // z = R (c - off): the basis reproduces constants, so shifting all
     // coefficients of a position shifts its curve
     const int b = axis * 2 + (I >= NV), kk = I % NV;
@@ -251,12 +263,14 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const double coff = (b == 0) ? offx : ((b == 2) ? offy : 0.0);
     double zz = 0.0;
     for (int j = kk; j < NV; ++j) zz += R[kk * NV + j] * (double(src[size_t(l) * NV + j]) - coff);
+    zl = zz;
+    vzd[axis * A2 + I] = zz;
     vz[axis * A2 + I] = T(zz);
     // lambda_z = R^-T lambda
     const T *glam = static_cast<const T *>(Dsrc.lam);
     double lz = 0.0;
     for (int j = 0; j <= kk; ++j) lz += Rinv[j * NV + kk] * double(glam[size_t(l) * 4 * NV + b * NV + j]);
-    lam = T(lz);
+    lam = lz;
   }
   if (hrow) {
     const int kk = lane;
@@ -275,6 +289,17 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     vaux[kk] = lampsi0;
   }
   wave_sync();
+  // H1 (A z - b) of the given coefficients (centred positions)
+  if (prow) {
+    const double *bb = axis == 0 ? Dsrc.bx : Dsrc.by;
+    const double off = axis == 0 ? offx : offy;
+    for (int e = 0; e < 6; ++e) {
+      double ae = 0.0;
+      for (int k = 0; k < NV; ++k) ae += Dsrc.Abc[e * NV + k] * vzd[axis * A2 + k];
+      const double be = (e == 0 || e == 3) ? bb[e] - off : bb[e];
+      bcc += Dsrc.H1d[I * 6 + e] * (ae - be);
+    }
+  }
   // mu = M2 lambda_psi (heading rows)
   T mu = T(0);
   if (hrow) {
@@ -283,21 +308,29 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   }
   wave_sync();
 
-  // ---- per-lane trajectory values at t
-  T x, xd, xdd, cc, y, yd, ydd, ss, psi, cps, sps, psih;
+  // ---- per-lane trajectory values at t: positions (absolute, FP64) and
+  // the other channels (T)
+  double xa, ya;
+  T xd, xdd, cc, yd, ydd, ss, psi, cps, sps, psih;
   T racc = T(0);   // sum over the iterations of psi_sign (psi - psi_hat) at t
 
   auto eval_xy = [&]() {
-    T a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    double a0 = 0.0, b0 = 0.0;
+    T a1 = 0, a2 = 0, a3 = 0, b1 = 0, b2 = 0, b3 = 0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       const T zx = vz[k], zc = vz[NV + k], zy = vz[A2 + k], zs = vz[A2 + NV + k];
-      a0 += Ub[k] * zx; a1 += Vb[k] * zx; a2 += Wb[k] * zx; a3 += Ub[k] * zc;
-      b0 += Ub[k] * zy; b1 += Vb[k] * zy; b2 += Wb[k] * zy; b3 += Ub[k] * zs;
+      a0 += Ubd[k] * vzd[k]; b0 += Ubd[k] * vzd[A2 + k];
+      a1 += Vb[k] * zx; a2 += Wb[k] * zx; a3 += Ub[k] * zc;
+      b1 += Vb[k] * zy; b2 += Wb[k] * zy; b3 += Ub[k] * zs;
     }
-    x = a0; xd = a1; xdd = a2; cc = a3;
-    y = b0; yd = b1; ydd = b2; ss = b3;
+    xa = a0 + offx; xd = a1; xdd = a2; cc = a3;
+    ya = b0 + offy; yd = b1; ydd = b2; ss = b3;
   };
+  // offset of this lane's robot centre from an obstacle centre, formed in
+  // FP64 and rounded once
+  auto off_x = [&](T ox) { return T(xa - double(ox)); };
+  auto off_y = [&](T oy) { return T(ya - double(oy)); };
   auto eval_psi = [&]() {
     T p = 0;
 #pragma unroll
@@ -318,7 +351,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // p = (a^2, b^2, ab, max(a, b)) of the inflated ellipse.
   T Sx[C], Sy[C];
   auto project_obstacle = [&](T ux, T uy, const Pair<T> o, const Quad<T> p) {
-    const T dxj = x - o.x, dyj = y - o.y;
+    const T dxj = off_x(o.x), dyj = off_y(o.y);
 #pragma unroll
     for (int i = 0; i < C; ++i) {
       if (i < m) {
@@ -345,6 +378,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const T ux = slack ? cc : cps, uy = slack ? ss : sps;
 #pragma unroll
     for (int i = 0; i < C; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
+    const T x = T(xa), y = T(ya);   // for the vote only
     if (!literal_alpha) {
       // Wave-wide vote: obstacles within ext + max(a, b) + margin of some
       // lane's robot centre, ext = max|r_i| |u| the reach of its circles.
@@ -413,7 +447,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 #pragma unroll
         for (int i = 0; i < C; ++i) {
           if (i < m) {
-            const T xt = x + rr[i] * ux - o.x, yt = y + rr[i] * uy - o.y;
+            const T xt = off_x(o.x) + rr[i] * ux, yt = off_y(o.y) + rr[i] * uy;
             const T xx = xt * xt, yy = yt * yt;
             const T kap = fmax(Num<T>::rsqrt(xx + yy), (a * xx + b * yy) / (a2 * xx + b2 * yy));
             Sx[i] += xt * (a * kap - T(1));
@@ -442,7 +476,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
           T sx = T(0), sy = T(0);
           for (int j = 0; j < n; ++j) {
             const Pair<T> o = oxy[j * q + tt];
-            const T xt = x + rr[i] * ux - o.x, yt = y + rr[i] * uy - o.y;
+            const T xt = off_x(o.x) + rr[i] * ux, yt = off_y(o.y) + rr[i] * uy;
             const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
             if (xt == T(0) && yt == T(0)) {
               sx += a;   // alpha = 0, d = 1: target (x_j + a, y_j)
@@ -516,34 +550,29 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   eval_xy();
   eval_psi();
   psih = psi;
-  // rows I of KKT^-1 (position block) and of F^T F: in registers for FP32
-  // under the two-wavefront register budget, else read from LDS
-  constexpr bool kRowsInRegs = RED == kRedRows && sizeof(T) == 4;
-  T m1row[A2], gfrow[A2];
-  if constexpr (kRowsInRegs) {
-    row_load<T, NV>(M1, I, m1row);
-    row_load<T, NV>(GF, I, gfrow);
-  }
-  auto m1_dot = [&](const T *v) {
-    if constexpr (kRowsInRegs) return row_dot_reg<T, NV>(m1row, v);
-    else return row_dot<T, NV>(M1, I, v);
-  };
-  auto gf_dot = [&](const T *v) {
-    if constexpr (kRowsInRegs) return row_dot_reg<T, NV>(gfrow, v);
-    else return row_dot<T, NV>(GF, I, v);
-  };
-  T gz = prow ? gf_dot(vz + axis * A2) : T(0);   // row of F^T F z
+  // rows I of M1 and N (position block), read from LDS in every product
+  auto m1_dot = [&](const double *v) { return row_dot<T, NV>(M1, I, v); };
+  auto n_dot = [&](const double *v) { return row_dot<T, NV>(NQ, I, v); };
+  double nz = n_dot(vzd + axis * A2);   // row of N z
   project_reduce(false);
-  if (prow) vrhs[axis * A2 + I] = lam + rho * (gz - tr);
+  if (prow) vwd[axis * A2 + I] = lam - rhod * double(tr);
   wave_sync();
 
   for (int it = 0; it < K; ++it) {
-    // ---- xi1: [z; mu] = KKT^-1 [lambda + rho F^T g; b]  (eqs. over_3, zeta_1_sepration_3)
-    if (prow) vz[axis * A2 + I] = hreg + m1_dot(vrhs + axis * A2);
+    // ---- xi1 (eqs. over_3, zeta_1_sepration_3) as an update of z:
+    // z' = z - H1 (A z - b) + M1 (lambda - rho F^T (F xi - g)) - N z
+    // (every lane computes; lanes past the position rows compute a copy of
+    // row 0 and store nothing)
+    zl += (m1_dot(vwd + axis * A2) - nz) - bcc;
+    bcc = 0.0;
+    if (prow) {
+      vzd[axis * A2 + I] = zl;
+      vz[axis * A2 + I] = T(zl);
+    }
     wave_sync();
     eval_xy();
-    // F^T F z of the new z, used by the next right-hand side
-    gz = prow ? gf_dot(vz + axis * A2) : T(0);
+    // N z of the new z, used by the next update
+    nz = n_dot(vzd + axis * A2);
 
     // ---- xi2: psi_hat = atan2(s, c) on the branch nearest psi^k, then the
     // heading QP (eq. compute_convex_surrogate):
@@ -569,8 +598,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     // ---- xi3, xi4 and the multipliers (eqs. update_lambda_1, update_lambda_psi)
     project_reduce(true);
     if (prow) {
-      lam -= rho * tr;
-      vrhs[axis * A2 + I] = lam + rho * (gz - tr);
+      lam -= rhod * double(tr);
+      vwd[axis * A2 + I] = lam - rhod * double(tr);
     }
     if (hrow) mu -= rhop * trpsi;
     wave_sync();
@@ -585,7 +614,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     if (lane < NV) xmine[kXchBig + lane] = s;
     __syncthreads();
     if (hrow) vaux[2 * A2 + lane] = lampsi0 - rhop * exchange_sum(kXchBig + lane);
-    if (prow) vaux[axis * A2 + I] = lam;
+    if (prow) vwd[axis * A2 + I] = lam;
     wave_sync();
   }
 
@@ -599,8 +628,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       const double coff = (b == 0) ? offx : ((b == 2) ? offy : 0.0);
       const int base = axis * A2 + (I >= NV ? NV : 0);
       double c = 0.0, lc = 0.0;
-      for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * double(vz[base + j]);
-      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(vaux[base + j]);
+      for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * vzd[base + j];
+      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * vwd[base + j];
       dst[size_t(l) * NV + kk] = T(c + coff);
       static_cast<T *>(Dsrc.lam)[size_t(l) * 4 * NV + b * NV + kk] = T(lc);
     }
@@ -618,8 +647,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // ---- optional outputs: trajectory and the final (alpha, d) of xi3/xi4
   if (Dsrc.traj) {
     T *trj = static_cast<T *>(Dsrc.traj) + size_t(l) * 3 * q;
-    trj[t] = x + T(offx);
-    trj[q + t] = y + T(offy);
+    trj[t] = T(xa);
+    trj[q + t] = T(ya);
     trj[2 * q + t] = psi;
   }
   if (Dsrc.va) {
@@ -639,8 +668,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < n; ++j) {
         const Pair<T> o = oxy[j * q + t];
-        const T xt = x + rr[i] * ux - o.x;
-        const T yt = y + rr[i] * uy - o.y;
+        const T xt = off_x(o.x) + rr[i] * ux;
+        const T yt = off_y(o.y) + rr[i] * uy;
         const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
         const T al = literal_alpha ? atan2z(yt, xt) : atan2z(a * yt, b * xt);
         const T ca = Num<T>::cos_(al), sa = Num<T>::sin_(al);
@@ -660,16 +689,16 @@ __device__ __forceinline__ void fused_block(const Desc &D) {
   T *lds = reinterpret_cast<T *>(smem_raw);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int q = uni(D.q), n = uni(D.n), B = uni(D.B), blk0 = uni(D.blk0);
-  const FusedLds L = fused_layout(q, n, NV, TILE, RED);
+  const FusedLds L = fused_layout(q, n, NV, TILE, RED, int(sizeof(double) / sizeof(T)));
   constexpr int N2 = 2 * NV, A2 = pad4(N2);
 
-  // block-wide: obstacle tables (centred, (x, y) pairs), inflated semi-axes,
+  // block-wide: obstacle tables ((x, y) pairs), inflated semi-axes,
   // operators as Quad [a2/4][2nv], zeroed per-wave areas (their padding
   // entries are read as zeros)
   const T *gox = static_cast<const T *>(D.ox), *goy = static_cast<const T *>(D.oy);
-  const T offx = T(D.offx), offy = T(D.offy), rc = T(D.rc);
+  const T rc = T(D.rc);
   Pair<T> *oxy = reinterpret_cast<Pair<T> *>(lds + L.oxy);
-  for (int i = tid; i < n * q; i += blockDim.x) oxy[i] = Pair<T>{gox[i] - offx, goy[i] - offy};
+  for (int i = tid; i < n * q; i += blockDim.x) oxy[i] = Pair<T>{gox[i], goy[i]};
   for (int j = tid; j < n; j += blockDim.x) {
     const T a = static_cast<const T *>(D.oa)[j] + rc;
     const T b = static_cast<const T *>(D.ob)[j] + rc;
@@ -677,12 +706,12 @@ __device__ __forceinline__ void fused_block(const Desc &D) {
     o[OP_A2] = a * a; o[OP_B2] = b * b; o[OP_AB] = a * b; o[OP_AMAX] = fmax(a, b);
     o[OP_A] = a; o[OP_B] = b; o[6] = T(0); o[7] = T(0);
   }
-  const T *gM1 = static_cast<const T *>(D.M1), *gGF = static_cast<const T *>(D.GF);
+  const T *gM1 = static_cast<const T *>(D.M1), *gN = static_cast<const T *>(D.N);
   for (int e = tid; e < A2 * N2; e += blockDim.x) {
     // element e of the Quad layout: chunk c, row I, component e % 4
     const int c = e / (4 * N2), rem = e % (4 * N2), I = rem / 4, J = 4 * c + rem % 4;
     lds[L.m1 + e] = J < N2 ? gM1[I * N2 + J] : T(0);
-    lds[L.gf + e] = J < N2 ? gGF[I * N2 + J] : T(0);
+    lds[L.gf + e] = J < N2 ? gN[I * N2 + J] : T(0);
   }
   for (int i = tid; i < 2 * TILE * L.wave_stride; i += blockDim.x) lds[L.wave0 + i] = T(0);
   __syncthreads();
@@ -758,7 +787,7 @@ hipError_t launch_f32(const Desc &single, const Desc *table, int nprob, int nblo
 }  // namespace
 
 size_t fused_lds_bytes(int q, int n, int nv, bool f64, int tile, int waves) {
-  return size_t(fused_layout(q, n, nv, tile, red_rows_for(waves)).total) * (f64 ? 8 : 4);
+  return size_t(fused_layout(q, n, nv, tile, red_rows_for(waves), f64 ? 1 : 2).total) * (f64 ? 8 : 4);
 }
 
 // FP64 kernels take the default budget only, built without a wavefront

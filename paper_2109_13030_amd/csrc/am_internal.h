@@ -27,8 +27,12 @@ struct Desc {
   const void *M1, *H1;       // xi1: [2nv][2nv] and [2nv][6]
   const void *M2, *H2;       // xi2: [nv][nv] and [nv][6]
   const void *GF;            // [2nv][2nv] F^T F of one axis in the z basis
+  const void *N;             // [2nv][2nv] M1 Q (Q: smoothness cost of one axis in the z basis)
   const void *Ut;            // [q][nv] U M2^T (heading rows premultiplied by M2)
   const double *R, *Rinv;    // z = R c (Bernstein c), [nv][nv]
+  const double *Ud;          // [q][nv] U in FP64 (positions)
+  const double *Abc;         // [6][nv] boundary rows U, V, W at t = 0 and t = q-1 (z basis)
+  const double *H1d;         // [2nv][6] H1 in FP64
   // problem
   const void *ox, *oy, *oa, *ob;
   // state (Bernstein coordinates at the boundary)
@@ -54,11 +58,13 @@ struct Consts {
   double *K1, *K2;               // z-space KKT [N1][N1], [N2][N2]
   double *A1, *A2;               // Gauss-Jordan work [N][2N]
   double *M1, *H1, *M2, *H2, *GF;
+  double *N;                     // [2nv][2nv] M1 Q
+  double *Abc;                   // [6][nv] boundary rows in the z basis
   double *K1b_inv, *K2b_inv;     // Bernstein-space inverses (diagnostics)
   double *Ut;                    // [q][nv] U M2^T
   double *status;                // [0]: 0 ok, 1 singular xi1 KKT, 2 singular xi2 KKT
   void *tU, *tV, *tW, *tM1, *tH1, *tM2, *tH2, *tGF;  // typed copies
-  void *tP, *tPd, *tPdd, *tUt;
+  void *tP, *tPd, *tPdd, *tUt, *tN;
 };
 
 // Launchers (defined in the .hip files).

@@ -8,6 +8,11 @@
 //
 // Per iteration:  xi1 -> evaluate -> xi2 -> project (alpha, d) ->
 //                 targets/residual channels -> reduce + multipliers.
+//
+// The xi1 step is the update form of the fused kernel,
+// z' = z - H1 (A z - b) + M1 (lambda - rho F^T (F xi - g)) - N z with N = M1 Q
+// (eq. over_3 and the identity M1 (Q + rho F^T F) + H1 A = I), and the
+// coefficients, multipliers and positions are kept in FP64 as there.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,12 +27,12 @@ constexpr int kThreads = 256;
 
 inline int blocks_for(size_t work) { return int((work + kThreads - 1) / kThreads); }
 
-// Workspace carve-up (elements of T).
+// Workspace carve-up (elements of T; dw elements of T per FP64 value).
 struct PlainWs {
-  size_t rhs, z, lam, zpsi, lampsi, traj8, psi3, psih, alpha, d, va4, chan, tot, total;
+  size_t wd, zd, zdn, lamd, xyd, z, zpsi, lampsi, traj8, psi3, psih, alpha, d, va4, chan, tot, total;
 };
 
-__host__ __device__ inline PlainWs plain_layout(int B, int q, int nv, int m, int n) {
+__host__ __device__ inline PlainWs plain_layout(int B, int q, int nv, int m, int n, int dw) {
   PlainWs w;
   size_t o = 0;
   auto take = [&](size_t cnt) {
@@ -35,9 +40,12 @@ __host__ __device__ inline PlainWs plain_layout(int B, int q, int nv, int m, int
     o += (cnt + 63) / 64 * 64;
     return at;
   };
-  w.rhs = take(size_t(B) * 4 * nv);
-  w.z = take(size_t(B) * 4 * nv);
-  w.lam = take(size_t(B) * 4 * nv);
+  w.wd = take(size_t(B) * 4 * nv * dw);     // lambda - rho F^T (F xi - g)
+  w.zd = take(size_t(B) * 4 * nv * dw);     // coefficients z (current) ...
+  w.zdn = take(size_t(B) * 4 * nv * dw);    // ... and after the next update
+  w.lamd = take(size_t(B) * 4 * nv * dw);   // multipliers
+  w.xyd = take(size_t(B) * 2 * q * dw);     // absolute positions x, y
+  w.z = take(size_t(B) * 4 * nv);           // T copy of z
   w.zpsi = take(size_t(B) * nv);
   w.lampsi = take(size_t(B) * nv);
   w.traj8 = take(size_t(B) * 8 * q);
@@ -54,14 +62,16 @@ __host__ __device__ inline PlainWs plain_layout(int B, int q, int nv, int m, int
 
 template <typename T>
 struct Ptrs {
-  T *rhs, *z, *lam, *zpsi, *lampsi, *traj8, *psi3, *psih, *alpha, *d, *va4, *chan, *tot;
+  double *wd, *zd, *zdn, *lamd, *xyd;
+  T *z, *zpsi, *lampsi, *traj8, *psi3, *psih, *alpha, *d, *va4, *chan, *tot;
 };
 
 template <typename T>
 Ptrs<T> ptrs_of(void *ws, const PlainWs &w) {
   T *b = static_cast<T *>(ws);
-  return Ptrs<T>{b + w.rhs, b + w.z, b + w.lam, b + w.zpsi, b + w.lampsi, b + w.traj8,
-                 b + w.psi3, b + w.psih, b + w.alpha, b + w.d, b + w.va4, b + w.chan, b + w.tot};
+  auto dp = [&](size_t o) { return reinterpret_cast<double *>(b + o); };
+  return Ptrs<T>{dp(w.wd), dp(w.zd), dp(w.zdn), dp(w.lamd), dp(w.xyd), b + w.z, b + w.zpsi, b + w.lampsi,
+                 b + w.traj8, b + w.psi3, b + w.psih, b + w.alpha, b + w.d, b + w.va4, b + w.chan, b + w.tot};
 }
 
 template <typename T>
@@ -85,8 +95,9 @@ __global__ void k_enter(Desc D, Ptrs<T> w) {
   if (b < 4) {
     const T *gl = static_cast<const T *>(D.lam) + size_t(l) * 4 * NV + b * NV;
     for (int j = 0; j <= kk; ++j) lz += Ri[j * NV + kk] * double(gl[j]);
+    w.zd[size_t(l) * 4 * NV + b * NV + kk] = z;
     w.z[size_t(l) * 4 * NV + b * NV + kk] = T(z);
-    w.lam[size_t(l) * 4 * NV + b * NV + kk] = T(lz);
+    w.lamd[size_t(l) * 4 * NV + b * NV + kk] = lz;
   } else {
     const T *gl = static_cast<const T *>(D.lampsi) + size_t(l) * NV;
     for (int j = 0; j <= kk; ++j) lz += Ri[j * NV + kk] * double(gl[j]);
@@ -95,24 +106,37 @@ __global__ void k_enter(Desc D, Ptrs<T> w) {
   }
 }
 
-// ---- xi1: z = M1 rhs + H1 b for both axes
+// ---- xi1 for both axes, as an update of z (read from zd, written to zdn):
+// z' = z - H1 (A z - b) + M1 w - N z, the boundary term on the first update
+// only (afterwards A z = b holds)
 template <typename T, int NV>
-__global__ void k_xi1(Desc D, Ptrs<T> w) {
+__global__ void k_xi1(Desc D, Ptrs<T> w, int first) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= D.B * 4 * NV) return;
   const int l = g / (4 * NV), k = g % (4 * NV), b = k / NV, kk = k % NV, axis = b >> 1;
   const int I = (b & 1) * NV + kk;
-  const T *M1 = static_cast<const T *>(D.M1), *H1 = static_cast<const T *>(D.H1);
-  const double *bb = axis == 0 ? D.bx : D.by;
-  const double off = axis == 0 ? D.offx : D.offy;
-  T acc = T(0);
-  for (int e = 0; e < 6; ++e) acc += H1[I * 6 + e] * T((e == 0 || e == 3) ? bb[e] - off : bb[e]);
-  const T *r = w.rhs + size_t(l) * 4 * NV + axis * 2 * NV;
-  for (int J = 0; J < 2 * NV; ++J) acc += M1[I * 2 * NV + J] * r[J];
-  w.z[size_t(l) * 4 * NV + k] = acc;
+  const T *M1 = static_cast<const T *>(D.M1), *NQ = static_cast<const T *>(D.N);
+  const double *r = w.wd + size_t(l) * 4 * NV + axis * 2 * NV;
+  const double *z = w.zd + size_t(l) * 4 * NV + axis * 2 * NV;
+  double acc = 0.0;
+  for (int J = 0; J < 2 * NV; ++J)
+    acc += double(M1[I * 2 * NV + J]) * r[J] - double(NQ[I * 2 * NV + J]) * z[J];
+  if (first) {
+    const double *bb = axis == 0 ? D.bx : D.by;
+    const double off = axis == 0 ? D.offx : D.offy;
+    for (int e = 0; e < 6; ++e) {
+      double ae = 0.0;
+      for (int j = 0; j < NV; ++j) ae += D.Abc[e * NV + j] * z[j];
+      acc -= D.H1d[I * 6 + e] * (ae - ((e == 0 || e == 3) ? bb[e] - off : bb[e]));
+    }
+  }
+  const double zn = z[I] + acc;
+  w.zdn[size_t(l) * 4 * NV + k] = zn;
+  w.z[size_t(l) * 4 * NV + k] = T(zn);
 }
 
-// ---- trajectories x, xdot, xddot, c, y, ydot, yddot, s on the grid
+// ---- trajectories on the grid: absolute positions x, y in FP64 (xyd) and
+// xdot, xddot, c, ydot, yddot, s in T (traj8 channels 1-3, 5-7)
 template <typename T, int NV>
 __global__ void k_eval(Desc D, Ptrs<T> w) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -120,15 +144,21 @@ __global__ void k_eval(Desc D, Ptrs<T> w) {
   const int l = g / D.q, t = g % D.q, q = D.q;
   const T *U = static_cast<const T *>(D.U) + t * NV, *V = static_cast<const T *>(D.V) + t * NV,
           *W = static_cast<const T *>(D.W) + t * NV;
+  const double *Ud = D.Ud + t * NV;
   const T *z = w.z + size_t(l) * 4 * NV;
+  const double *zd = w.zd + size_t(l) * 4 * NV;
   T v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double x = 0.0, y = 0.0;
   for (int k = 0; k < NV; ++k) {
-    v[0] += U[k] * z[k]; v[1] += V[k] * z[k]; v[2] += W[k] * z[k]; v[3] += U[k] * z[NV + k];
-    v[4] += U[k] * z[2 * NV + k]; v[5] += V[k] * z[2 * NV + k]; v[6] += W[k] * z[2 * NV + k];
-    v[7] += U[k] * z[3 * NV + k];
+    x += Ud[k] * zd[k]; y += Ud[k] * zd[2 * NV + k];
+    v[1] += V[k] * z[k]; v[2] += W[k] * z[k]; v[3] += U[k] * z[NV + k];
+    v[5] += V[k] * z[2 * NV + k]; v[6] += W[k] * z[2 * NV + k]; v[7] += U[k] * z[3 * NV + k];
   }
+  w.xyd[size_t(l) * 2 * q + t] = x + D.offx;
+  w.xyd[size_t(l) * 2 * q + q + t] = y + D.offy;
   T *o = w.traj8 + size_t(l) * 8 * q + t;
-  for (int c = 0; c < 8; ++c) o[c * q] = v[c];
+  for (int c = 0; c < 8; ++c)
+    if (c != 0 && c != 4) o[c * q] = v[c];
 }
 
 // ---- heading trajectory psi = U z_psi with cos, sin
@@ -207,6 +237,23 @@ template <typename T, int V>
 __device__ __forceinline__ Vec<T, V> ldv(const T *p) {
   return *reinterpret_cast<const Vec<T, V> *>(p);
 }
+// V consecutive FP64 values in loads of at most 16 bytes (the workspace is
+// only 16-byte aligned)
+template <int V>
+__device__ __forceinline__ Vec<double, V> ldd(const double *p) {
+  Vec<double, V> r;
+  if constexpr (V == 1) {
+    r.v[0] = p[0];
+  } else {
+#pragma unroll
+    for (int e = 0; e < V; e += 2) {
+      const Vec<double, 2> h = *reinterpret_cast<const Vec<double, 2> *>(p + e);
+      r.v[e] = h.v[0];
+      r.v[e + 1] = h.v[1];
+    }
+  }
+  return r;
+}
 template <typename T, int V>
 __device__ __forceinline__ void stv(T *p, const Vec<T, V> &x) {
   *reinterpret_cast<Vec<T, V> *>(p) = x;
@@ -241,17 +288,17 @@ __global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
   const int l = g / per, k = g - l * per;
   const int i = k / qv, t = (k - i * qv) * V;
   const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
-  const T offx = T(D.offx), offy = T(D.offy);
   if (i < m) {
     const T ri = T(D.r[i]);
-    const Vec<T, V> xv = ldv<T, V>(tr + t), yv = ldv<T, V>(tr + 4 * q + t);
+    const double *xyl = w.xyd + size_t(l) * 2 * q;
+    const Vec<double, V> xv = ldd<V>(xyl + t), yv = ldd<V>(xyl + q + t);
     const Vec<T, V> uxv = slack ? ldv<T, V>(tr + 3 * q + t) : ldv<T, V>(p3 + q + t);
     const Vec<T, V> uyv = slack ? ldv<T, V>(tr + 7 * q + t) : ldv<T, V>(p3 + 2 * q + t);
-    T px[V], py[V];
+    T rx[V], ry[V];
 #pragma unroll
     for (int e = 0; e < V; ++e) {
-      px[e] = xv.v[e] + ri * uxv.v[e];
-      py[e] = yv.v[e] + ri * uyv.v[e];
+      rx[e] = ri * uxv.v[e];
+      ry[e] = ri * uyv.v[e];
     }
     const size_t row0 = (size_t(l) * m + i) * n;
     T *oal = w.alpha + row0 * q + t, *od = w.d + row0 * q + t;
@@ -275,7 +322,9 @@ __global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
         Vec<T, V> al, dd;
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-          const T xt = px[e] - (gx[u].v[e] - offx), yt = py[e] - (gy[u].v[e] - offy);
+          // offset of the robot centre from the obstacle centre in FP64,
+          // rounded once
+          const T xt = T(xv.v[e] - double(gx[u].v[e])) + rx[e], yt = T(yv.v[e] - double(gy[u].v[e])) + ry[e];
           if (!literal) {
             // elliptic angle: the point (a d cos al, b d sin al) is (xt, yt)
             // itself, so d = sqrt(xt^2/a^2 + yt^2/b^2) (eq. compute_zeta_3)
@@ -349,10 +398,11 @@ __global__ __launch_bounds__(kItemThreads) void k_targets(Desc D, Ptrs<T> w) {
   // V consecutive time steps per item (V = 2 when q is even: every row
   // offset is then even, so the pairs are aligned vector loads)
   const int qv = q / V;
+  const double *xyl = w.xyd + size_t(l) * 2 * q;
   for (int k = threadIdx.x; k < m * qv; k += blockDim.x) {
     const int i = k / qv, t = (k - i * qv) * V;
-    const Vec<T, V> xv = ldv<T, V>(tr + t), cv = ldv<T, V>(tr + 3 * q + t), yv = ldv<T, V>(tr + 4 * q + t),
-                    sv = ldv<T, V>(tr + 7 * q + t);
+    const Vec<T, V> cv = ldv<T, V>(tr + 3 * q + t), sv = ldv<T, V>(tr + 7 * q + t);
+    const Vec<double, V> xv = ldd<V>(xyl + t), yv = ldd<V>(xyl + q + t);
     const Vec<T, V> uxv = slack ? cv : ldv<T, V>(p3 + q + t), uyv = slack ? sv : ldv<T, V>(p3 + 2 * q + t);
     const T ri = T(D.r[i]);
     const size_t base = (size_t(l) * m + i) * n * q + t;
@@ -391,11 +441,12 @@ __global__ __launch_bounds__(kItemThreads) void k_targets(Desc D, Ptrs<T> w) {
 #pragma unroll
           for (int e = 0; e < V; ++e) {
             if (literal || dv[u].v[e] <= T(1)) {
-              const T oxj = gx.v[e] - T(D.offx), oyj = gy.v[e] - T(D.offy);
+              const T xt = T(xv.v[e] - double(gx.v[e])) + ri * uxv.v[e];
+              const T yt = T(yv.v[e] - double(gy.v[e])) + ri * uyv.v[e];
               T sa, ca;
               Num<T>::sincos_(av.v[e], &sa, &ca);
-              sx[e] += ell[0][j] * dv[u].v[e] * ca - (xv.v[e] + ri * uxv.v[e] - oxj);
-              sy[e] += ell[1][j] * dv[u].v[e] * sa - (yv.v[e] + ri * uyv.v[e] - oyj);
+              sx[e] += ell[0][j] * dv[u].v[e] * ca - xt;
+              sy[e] += ell[1][j] * dv[u].v[e] * sa - yt;
             }
           }
         }
@@ -467,7 +518,6 @@ __global__ void k_contract(Desc D, Ptrs<T> w, int update) {
   if (l >= D.B) return;
   const int q = D.q;
   const T *U = static_cast<const T *>(D.U), *V = static_cast<const T *>(D.V), *W = static_cast<const T *>(D.W);
-  const T *GF = static_cast<const T *>(D.GF);
   const T *ch = w.chan + size_t(l) * 9 * q;
   T part[5 * NV];
   for (int k = 0; k < 5 * NV; ++k) part[k] = T(0);
@@ -483,18 +533,16 @@ __global__ void k_contract(Desc D, Ptrs<T> w, int update) {
   }
   T tot[5 * NV];
   for (int k = 0; k < 5 * NV; ++k) tot[k] = wsum(part[k]);
-  T *lam = w.lam + size_t(l) * 4 * NV, *z = w.z + size_t(l) * 4 * NV;
+  double *lam = w.lamd + size_t(l) * 4 * NV;
   if (lane < 4 * NV) {
-    const int k = lane, b = k / NV, kk = k % NV, axis = b >> 1, I = (b & 1) * NV + kk;
+    const int k = lane;
     T trv = T(0);
     for (int c = 0; c < 4 * NV; ++c)
       if (c == k) trv = tot[c];
-    T lv = lam[k];
-    if (update) lv -= T(D.rho) * trv;
-    T gz = T(0);
-    for (int J = 0; J < 2 * NV; ++J) gz += GF[I * 2 * NV + J] * z[axis * 2 * NV + J];
+    double lv = lam[k];
+    if (update) lv -= D.rho * double(trv);
     lam[k] = lv;
-    w.rhs[size_t(l) * 4 * NV + k] = lv + T(D.rho) * (gz - trv);
+    w.wd[size_t(l) * 4 * NV + k] = lv - D.rho * double(trv);
   } else if (update && lane < 5 * NV) {
     const int kk = lane - 4 * NV;
     T tp = T(0);
@@ -579,51 +627,7 @@ __global__ void k_contract_mfma(Desc D, Ptrs<float> w) {
   }
 }
 
-// ---- xi1 on the matrix cores (with AM_PLAIN_BF16X3): per axis the batch's
-// right-hand sides times M1^T, Z[16 traj x 2nv] = RHS[16 x 2nv] M1^T, as
-// 16 x 16 output tiles over k steps of 4 (2nv padded to a multiple of 4)
-// with v_mfma_f32_16x16x4_f32: FP32 operands and accumulation.  (The BF16
-// split used for the contraction is not accurate enough here: z = M1 rhs
-// cancels large terms of rhs, and the split's 2^-17 relative product error
-// moved the final trajectories by ~1e-3 m on c4.)  Lane L supplies
-// A[traj L%16][k L/16] and B[k L/16][out L%16] and receives
-// D[traj 4(L/16)+i][out L%16].  One wavefront per 16 trajectories and axis.
-template <int NV>
-__global__ void k_xi1_mfma(Desc D, Ptrs<float> w) {
-  constexpr int N2 = 2 * NV;
-  static_assert(N2 <= 32, "two 16-wide tiles");
-  const int lane = threadIdx.x & 63;
-  const int task = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  const int tiles = (D.B + 15) / 16;
-  if (task >= 2 * tiles) return;
-  const int axis = task / tiles, l0 = (task % tiles) * 16, B = D.B;
-  const int r = lane & 15, kk = lane >> 4;
-  const int la = l0 + r;
-  const float *M1 = static_cast<const float *>(D.M1), *H1 = static_cast<const float *>(D.H1);
-  const double *bb = axis == 0 ? D.bx : D.by;
-  const double off = axis == 0 ? D.offx : D.offy;
-  for (int n0 = 0; n0 < N2; n0 += 16) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int out = n0 + r;
-    for (int k0 = 0; k0 < N2; k0 += 4) {
-      const int k = k0 + kk;
-      const float av = (la < B && k < N2) ? w.rhs[size_t(la) * 4 * NV + axis * N2 + k] : 0.f;
-      const float bv = (out < N2 && k < N2) ? M1[out * N2 + k] : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
-    }
-    if (out < N2) {
-      float h = 0.f;
-      for (int e = 0; e < 6; ++e) h += H1[out * 6 + e] * float((e == 0 || e == 3) ? bb[e] - off : bb[e]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int lt = l0 + kk * 4 + i;
-        if (lt < B) w.z[size_t(lt) * 4 * NV + axis * N2 + out] = acc[i] + h;
-      }
-    }
-  }
-}
-
-// ---- multipliers and the next right-hand side from the contraction totals
+// ---- multipliers and the next xi1 right-hand side from the contraction totals
 template <typename T, int NV>
 __global__ void k_update(Desc D, Ptrs<T> w, int update) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -631,14 +635,10 @@ __global__ void k_update(Desc D, Ptrs<T> w, int update) {
   const int l = g / (5 * NV), k = g % (5 * NV);
   const T trv = w.tot[size_t(l) * 5 * NV + k];
   if (k < 4 * NV) {
-    const int b = k / NV, kk = k % NV, axis = b >> 1, I = (b & 1) * NV + kk;
-    const T *GF = static_cast<const T *>(D.GF), *z = w.z + size_t(l) * 4 * NV;
-    T lv = w.lam[size_t(l) * 4 * NV + k];
-    if (update) lv -= T(D.rho) * trv;
-    T gz = T(0);
-    for (int J = 0; J < 2 * NV; ++J) gz += GF[I * 2 * NV + J] * z[axis * 2 * NV + J];
-    w.lam[size_t(l) * 4 * NV + k] = lv;
-    w.rhs[size_t(l) * 4 * NV + k] = lv + T(D.rho) * (gz - trv);
+    double lv = w.lamd[size_t(l) * 4 * NV + k];
+    if (update) lv -= D.rho * double(trv);
+    w.lamd[size_t(l) * 4 * NV + k] = lv;
+    w.wd[size_t(l) * 4 * NV + k] = lv - D.rho * double(trv);
   } else if (update) {
     w.lampsi[size_t(l) * NV + (k - 4 * NV)] -= T(D.rho_psi) * trv;
   }
@@ -651,11 +651,16 @@ __global__ void k_exit(Desc D, Ptrs<T> w) {
   if (g < D.B * 5 * NV) {
     const int l = g / (5 * NV), k = g % (5 * NV), b = k / NV, kk = k % NV;
     const double *R = D.R, *Ri = D.Rinv;
-    const T *zs = b < 4 ? w.z + size_t(l) * 4 * NV + b * NV : w.zpsi + size_t(l) * NV;
-    const T *ls = b < 4 ? w.lam + size_t(l) * 4 * NV + b * NV : w.lampsi + size_t(l) * NV;
     double c = 0.0, lc = 0.0;
-    for (int j = kk; j < NV; ++j) c += Ri[kk * NV + j] * double(zs[j]);
-    for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(ls[j]);
+    if (b < 4) {
+      const double *zs = w.zd + size_t(l) * 4 * NV + b * NV, *ls = w.lamd + size_t(l) * 4 * NV + b * NV;
+      for (int j = kk; j < NV; ++j) c += Ri[kk * NV + j] * zs[j];
+      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * ls[j];
+    } else {
+      const T *zs = w.zpsi + size_t(l) * NV, *ls = w.lampsi + size_t(l) * NV;
+      for (int j = kk; j < NV; ++j) c += Ri[kk * NV + j] * double(zs[j]);
+      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(ls[j]);
+    }
     const double off = b == 0 ? D.offx : (b == 2 ? D.offy : 0.0);
     T *dst = static_cast<T *>(b == 0 ? D.cx : b == 1 ? D.cc : b == 2 ? D.cy : b == 3 ? D.cs : D.cpsi);
     dst[size_t(l) * NV + kk] = T(c + off);
@@ -665,11 +670,11 @@ __global__ void k_exit(Desc D, Ptrs<T> w) {
   const int q = D.q;
   if (g < D.B * q) {
     const int l = g / q, t = g % q;
-    const T *tr = w.traj8 + size_t(l) * 8 * q, *p3 = w.psi3 + size_t(l) * 3 * q;
+    const T *p3 = w.psi3 + size_t(l) * 3 * q;
     if (D.traj) {
       T *o = static_cast<T *>(D.traj) + size_t(l) * 3 * q;
-      o[t] = tr[t] + T(D.offx);
-      o[q + t] = tr[4 * q + t] + T(D.offy);
+      o[t] = T(w.xyd[size_t(l) * 2 * q + t]);
+      o[q + t] = T(w.xyd[size_t(l) * 2 * q + q + t]);
       o[2 * q + t] = p3[t];
     }
     if (D.va) {
@@ -701,16 +706,13 @@ void contract(const Desc &D, const Ptrs<T> &w, hipStream_t st, int update) {
   hipLaunchKernelGGL((k_contract<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w, update);
 }
 
+// The update reads zd and writes zdn; the two buffers then swap.
 template <typename T, int NV>
-void xi1(const Desc &D, const Ptrs<T> &w, hipStream_t st) {
-  if constexpr (sizeof(T) == 4) {
-    if (D.flags & AM_PLAIN_BF16X3) {
-      const int tasks = 2 * ((D.B + 15) / 16);
-      hipLaunchKernelGGL((k_xi1_mfma<NV>), dim3((tasks + 3) / 4), dim3(kThreads), 0, st, D, w);
-      return;
-    }
-  }
-  hipLaunchKernelGGL((k_xi1<T, NV>), dim3(blocks_for(size_t(D.B) * 4 * NV)), dim3(kThreads), 0, st, D, w);
+void xi1(const Desc &D, Ptrs<T> &w, hipStream_t st, int first) {
+  hipLaunchKernelGGL((k_xi1<T, NV>), dim3(blocks_for(size_t(D.B) * 4 * NV)), dim3(kThreads), 0, st, D, w, first);
+  double *t = w.zd;
+  w.zd = w.zdn;
+  w.zdn = t;
 }
 
 // Four time steps per item once the batch gives every SIMD about four
@@ -730,8 +732,8 @@ void targets(const Desc &D, const Ptrs<T> &w, hipStream_t st) {
 
 template <typename T, int NV>
 hipError_t run(const Desc &D, void *ws, hipStream_t st) {
-  const PlainWs L = plain_layout(D.B, D.q, NV, D.m, D.n);
-  const Ptrs<T> w = ptrs_of<T>(ws, L);
+  const PlainWs L = plain_layout(D.B, D.q, NV, D.m, D.n, int(sizeof(double) / sizeof(T)));
+  Ptrs<T> w = ptrs_of<T>(ws, L);
   const int B = D.B, q = D.q;
   const int wave_blocks = (B + 3) / 4;
   hipLaunchKernelGGL((k_enter<T, NV>), dim3(blocks_for(size_t(B) * 5 * NV)), dim3(kThreads), 0, st, D, w);
@@ -742,7 +744,7 @@ hipError_t run(const Desc &D, void *ws, hipStream_t st) {
   targets<T>(D, w, st);
   contract<T, NV>(D, w, st, 0);
   for (int it = 0; it < D.K; ++it) {
-    xi1<T, NV>(D, w, st);
+    xi1<T, NV>(D, w, st, it == 0);
     hipLaunchKernelGGL((k_eval<T, NV>), dim3(blocks_for(size_t(B) * q)), dim3(kThreads), 0, st, D, w);
     hipLaunchKernelGGL((k_xi2<T, NV>), dim3(wave_blocks), dim3(kThreads), 0, st, D, w);
     project<T>(D, w, st);
@@ -757,7 +759,7 @@ hipError_t run(const Desc &D, void *ws, hipStream_t st) {
 }  // namespace
 
 size_t plain_workspace_bytes(int B, int q, int nv, int m, int n, bool f64) {
-  return plain_layout(B, q, nv, m, n).total * (f64 ? 8 : 4);
+  return plain_layout(B, q, nv, m, n, f64 ? 1 : 2).total * (f64 ? 8 : 4);
 }
 
 hipError_t launch_plain(const Desc &d, void *ws, size_t, bool f64, int nv, hipStream_t st) {

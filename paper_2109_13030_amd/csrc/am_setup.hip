@@ -292,6 +292,20 @@ __global__ __launch_bounds__(kSetupThreads) void setup_kernel(SetupArgs a) {
   }
   __syncthreads();
 
+  // N = M1 Q with Q the smoothness block of the xi1 objective (the same
+  // blocks as in A1); boundary rows of the position block in the z basis
+  for (int idx = tid; idx < n2 * n2; idx += kSetupThreads) {
+    const int I = idx / n2, J = idx % n2, bj = J / nv, j = J % nv;
+    double v = 0.0;
+    if (bj == 0 || q_cs)
+      for (int k = 0; k < nv; ++k) v += c.M1[I * n2 + bj * nv + k] * GWW[k * nv + j];
+    c.N[idx] = v;
+  }
+  for (int idx = tid; idx < 6 * nv; idx += kSetupThreads) {
+    const int e = idx / nv, k = idx % nv, t = e < 3 ? 0 : q - 1;
+    const double *X = (e % 3 == 0) ? c.U : ((e % 3 == 1) ? c.V : c.W);
+    c.Abc[idx] = X[t * nv + k];
+  }
   // U~ = U M2^T: the heading step's rows premultiplied by M2
   for (int idx = tid; idx < q * nv; idx += kSetupThreads) {
     const int t = idx / nv, k = idx % nv;
@@ -309,6 +323,7 @@ __global__ __launch_bounds__(kSetupThreads) void setup_kernel(SetupArgs a) {
     to_typed<double>(c.H2, c.tH2, nv * 6); to_typed<double>(c.GF, c.tGF, n2 * n2);
     to_typed<double>(c.P, c.tP, q * nv); to_typed<double>(c.Pd, c.tPd, q * nv);
     to_typed<double>(c.Pdd, c.tPdd, q * nv); to_typed<double>(c.Ut, c.tUt, q * nv);
+    to_typed<double>(c.N, c.tN, n2 * n2);
   } else {
     to_typed<float>(c.U, c.tU, q * nv); to_typed<float>(c.V, c.tV, q * nv);
     to_typed<float>(c.W, c.tW, q * nv); to_typed<float>(c.M1, c.tM1, n2 * n2);
@@ -316,6 +331,7 @@ __global__ __launch_bounds__(kSetupThreads) void setup_kernel(SetupArgs a) {
     to_typed<float>(c.H2, c.tH2, nv * 6); to_typed<float>(c.GF, c.tGF, n2 * n2);
     to_typed<float>(c.P, c.tP, q * nv); to_typed<float>(c.Pd, c.tPd, q * nv);
     to_typed<float>(c.Pdd, c.tPdd, q * nv); to_typed<float>(c.Ut, c.tUt, q * nv);
+    to_typed<float>(c.N, c.tN, n2 * n2);
   }
 }
 

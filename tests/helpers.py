@@ -9,11 +9,21 @@ import oracle
 # FP32 parity tolerance of the fixed-iteration solve against the FP64 oracle
 TOL_POS = 1e-3   # m
 TOL_PSI = 1e-3   # rad
-# A trajectory is well conditioned when the FP64 oracle itself moves by no
-# more than TOL/20 under a relative perturbation of 2^-24 of its initial
-# coefficients (the rounding of an FP32 input).  Only for those does a
-# 1e-3 agreement of an FP32 computation follow from the arithmetic.
-COND_FRACTION = 1.0 / 20.0
+
+
+def as_stored(pb: dict, init: dict, dtype: str):
+    """The problem and initial state as the device arrays of `dtype` hold
+    them: for FP32 the obstacle table and the initial coefficients and
+    multipliers rounded once to float32 (the scalars of the problem travel
+    as doubles through the C-ABI).  The oracle is run on these values, so
+    that a parity test measures the arithmetic of the path and not the
+    quantisation of its inputs."""
+    if dtype != "f32":
+        return pb, init
+    r32 = lambda v: np.asarray(np.asarray(v, np.float64), np.float32).astype(np.float64)
+    pb = dict(pb, **{k: r32(pb[k]) for k in ("ox", "oy", "oa", "ob")})
+    init = {k: r32(v) for k, v in init.items()}
+    return pb, init
 
 
 def subset(init: dict, idx) -> dict:
@@ -58,23 +68,3 @@ def traj_errors(pb: dict, out: dict, orc, st):
     epos = np.maximum(np.abs(gx - ox).max(1), np.abs(gy - oy).max(1))
     epsi = np.abs(gp - op).max(1)
     return epos, epsi
-
-
-def conditioning(pb: dict, init: dict, K: int, trials: int = 2, seed: int = 7, nthreads: int = 0):
-    """Per-trajectory spread of the FP64 oracle result under 2^-24 relative
-    perturbations of the initial coefficients (max over trials of max |dx|,
-    |dy|, |dpsi|)."""
-    orc, st = run_oracle(pb, init, K, nthreads=nthreads)
-    x0, y0, p0 = oracle_traj(orc, st)
-    rng = np.random.default_rng(seed)
-    spread = np.zeros(x0.shape[0])
-    for _ in range(trials):
-        pert = dict(init)
-        for k in ("cx", "cy"):
-            v = np.asarray(init[k], np.float64)
-            pert[k] = v * (1.0 + 2.0 ** -24 * rng.choice([-1.0, 1.0], v.shape))
-        o2, s2 = run_oracle(pb, pert, K, nthreads=nthreads)
-        x, y, p = oracle_traj(o2, s2)
-        spread = np.maximum(spread, np.maximum(np.abs(x - x0).max(1), np.maximum(np.abs(y - y0).max(1),
-                                                                                  np.abs(p - p0).max(1))))
-    return orc, st, spread

@@ -615,3 +615,20 @@ def test_invalid_problem_rejected():
         oracle.Oracle(dict(pb, vmax=-1.0))
     with pytest.raises(ValueError):
         oracle.Oracle(dict(pb, q=1))
+
+
+def test_fp32_input_rounding_is_amplified():
+    """Why FP32 parity is stated on the FP32 inputs: rounding c2 trajectory
+    809's initial coefficients and the obstacle table to float32 (a relative
+    change of at most 2^-24) moves its FP64 oracle result after the 100
+    iterations of Sec. III-D by more than the 1e-3 m tolerance."""
+    from tests import helpers as H
+    pb, init = inputs.workload("c2")
+    one = H.subset(init, [809])
+    orc, st = H.run_oracle(pb, one, 100)
+    pb32, one32 = H.as_stored(pb, one, "f32")
+    orc32, st32 = H.run_oracle(pb32, one32, 100)
+    x, y, _ = orc.trajectories(st)
+    x32, y32, _ = orc32.trajectories(st32)
+    move = max(np.abs(x - x32).max(), np.abs(y - y32).max())
+    assert move > 1e-3, move
