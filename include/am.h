@@ -200,6 +200,20 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
                    const int32_t *batch, const int32_t *iters, const am_state *states,
                    void *workspace, size_t workspace_bytes, void *stream);
 
+/* am_solve_multi for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same launch, with the problem table in the library's static device
+ * array of AM_STATIC_MAX_PROBLEMS descriptors instead of a workspace.  Each
+ * GPU holds its own copy of that array until the process ends; this call
+ * allocates nothing.  nprob > AM_STATIC_MAX_PROBLEMS returns AM_ERR_INVALID
+ * before any launch.  The table is written on `stream` and read by the
+ * launch that follows it there: calls that overlap on one GPU (on two
+ * streams, or from two threads) share the array and race, so callers
+ * serialise them.  Other arguments and errors as for am_solve_multi. */
+#define AM_STATIC_MAX_PROBLEMS 128
+int am_solve_multi_static(int32_t nprob, am_handle *const *handles, const am_problem *problems,
+                          const int32_t *batch, const int32_t *iters, const am_state *states, void *stream);
+
 /* Launch configuration of the one-launch solve (the arithmetic, and so the
  * result, is the same for every configuration):
  * - tile: trajectories per 2*64*tile-thread block (two wavefronts per

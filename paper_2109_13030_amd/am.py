@@ -28,7 +28,9 @@ EXPORTS = ("am_setup", "am_destroy", "am_last_error", "am_solve_batch", "am_plai
            "am_solve_batch_plain", "am_multi_workspace_size", "am_solve_multi", "am_residuals",
            "am_setup_matrices", "am_server_create", "am_server_submit", "am_server_wait",
            "am_server_stats", "am_server_destroy", "am_set_tile", "am_get_tile", "am_autotune",
-           "am_autotune_multi", "am_select_best", "am_server_best", "am_set_waves", "am_get_waves")
+           "am_autotune_multi", "am_select_best", "am_server_best", "am_set_waves", "am_get_waves",
+           "am_solve_multi_static")
+STATIC_MAX_PROBLEMS = 128   # AM_STATIC_MAX_PROBLEMS
 TILES = (1, 2, 4)
 WAVES = (2, 3)
 LAUNCHES = tuple((t, w) for w in WAVES for t in TILES)   # order of the autotuner's times
@@ -112,6 +114,8 @@ def lib():
         L.am_get_waves.argtypes = [vp, ct.POINTER(i32)]
         L.am_autotune.argtypes = [vp, ct.POINTER(Problem), i32, i32, ct.POINTER(State), vp, ct.POINTER(i32),
                                   ct.POINTER(i32), ct.POINTER(ct.c_float)]
+        L.am_solve_multi_static.argtypes = [i32, ct.POINTER(vp), ct.POINTER(Problem), ct.POINTER(i32),
+                                            ct.POINTER(i32), ct.POINTER(State), vp]
         L.am_autotune_multi.argtypes = [i32, ct.POINTER(vp), ct.POINTER(Problem), ct.POINTER(i32), ct.POINTER(i32),
                                         ct.POINTER(State), vp, sz, vp, ct.POINTER(i32), ct.POINTER(i32),
                                         ct.POINTER(ct.c_float)]
@@ -315,6 +319,18 @@ def solve_multi(handles, problems, states, iters, workspace, stream=None):
     S = (State * k)(*[s.c for s in states])
     check(lib().am_solve_multi(k, H, P, Bs, Ks, S, _ptr(workspace), workspace.numel() * workspace.element_size(),
                                _stream_ptr(stream)))
+
+
+def solve_multi_static(handles, problems, states, iters, stream=None):
+    """am_solve_multi with the problem table in the library's static device
+    array (no workspace, nothing allocated)."""
+    k = len(handles)
+    H = (ct.c_void_p * max(k, 1))(*[h.ptr.value for h in handles])
+    P = (Problem * max(k, 1))(*[p.c for p in problems])
+    Bs = (ct.c_int32 * max(k, 1))(*[s.B for s in states])
+    Ks = (ct.c_int32 * max(k, 1))(*([int(iters)] * k if np.isscalar(iters) else [int(v) for v in iters]))
+    S = (State * max(k, 1))(*[s.c for s in states])
+    check(lib().am_solve_multi_static(k, H, P, Bs, Ks, S, _stream_ptr(stream)))
 
 
 def autotune(h: Handle, p: DeviceProblem, scratch: DeviceState, iters: int, stream=None):

@@ -15,7 +15,8 @@ BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("AM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["am_api.cpp", "am_server.cpp", "am_setup.hip", "am_fused.hip", "am_residuals.hip", "am_plain.hip"]
+SOURCES = ["am_api.cpp", "am_server.cpp", "am_setup.hip", "am_fused.hip", "am_residuals.hip", "am_plain.hip",
+           "am_static.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
           "-Wall", "-Wno-unused-function"]

@@ -9,7 +9,6 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
-#include <vector>
 
 #include "am.h"
 #include "am_internal.h"
@@ -279,6 +278,12 @@ int am_setup(const am_shape *s, am_handle **out) {
               status == 1.0 ? "xi1" : "xi2");
   }
   if (stream) (void)hipStreamDestroy(stream);
+  if (rc == AM_OK) {
+    // the static problem table of am_solve_multi_static: its device address
+    // on this device, looked up once with the device current
+    amk::Desc *tbl = nullptr;
+    if ((e = amk::static_table(h->device, &tbl)) != hipSuccess) rc = hip_fail(e, "static problem table");
+  }
   if (rc != AM_OK) {
     am_destroy(h);
     return rc;
@@ -321,20 +326,20 @@ int am_multi_workspace_size(int32_t nprob, size_t *bytes) {
   return AM_OK;
 }
 
-int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *problems, const int32_t *batch,
-                   const int32_t *iters, const am_state *states, void *workspace, size_t workspace_bytes,
-                   void *stream) {
-  if (nprob < 0 || nprob > amk::kMaxProblems)
-    return fail(AM_ERR_INVALID, "nprob must be in [0, %d]", amk::kMaxProblems);
+}  // extern "C"
+
+namespace {
+
+// The multi-problem launch with its problem table at `table` (device memory
+// for at least `cap` descriptors).  Two passes over the problems: the first
+// checks them and sizes the launch, the second writes the table in chunks
+// through kernel arguments; no host or device memory is allocated.
+int solve_multi_into(int32_t nprob, am_handle *const *handles, const am_problem *problems, const int32_t *batch,
+                     const int32_t *iters, const am_state *states, Desc *table, int cap, void *stream) {
+  if (nprob < 0 || nprob > cap) return fail(AM_ERR_INVALID, "nprob must be in [0, %d]", cap);
   if (nprob == 0) return AM_OK;
   if (!handles || !problems || !batch || !iters || !states)
     return fail(AM_ERR_INVALID, "problem arrays must be non-NULL");
-  size_t need = 0;
-  am_multi_workspace_size(nprob, &need);
-  if (!workspace || workspace_bytes < need)
-    return fail(AM_ERR_INVALID, "workspace of %zu bytes needed", need);
-  std::vector<Desc> descs;
-  descs.reserve(nprob);
   const am_handle *h0 = handles[0];
   if (!h0) return fail(AM_ERR_INVALID, "handle 0 is NULL");
   size_t lds = 0;
@@ -349,10 +354,7 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
     if ((rc = check_problem(h, &problems[k])) != AM_OK) return rc;
     if (batch[k] > 0 && (rc = check_state(&states[k])) != AM_OK) return rc;
     if ((rc = check_device(h)) != AM_OK) return rc;
-    Desc d = make_desc(h, &problems[k], batch[k], iters[k], &states[k], h0->tile);
-    d.blk0 = blocks;
-    blocks += d.nblk;
-    descs.push_back(d);
+    blocks += (batch[k] + h0->tile - 1) / h0->tile;
     lds = std::max(lds, amk::fused_lds_bytes(h->shape.q, h->shape.n_obs, h->shape.nv, h->f64, h0->tile, h0->waves));
     max_m = std::max(max_m, int(h->shape.m));
   }
@@ -360,12 +362,57 @@ int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *p
     return fail(AM_ERR_INVALID, "a problem needs %zu bytes of LDS, device allows %zu", lds, lds_limit());
   if (blocks == 0) return AM_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  Desc *table = static_cast<Desc *>(workspace);
-  hipError_t e = amk::launch_desc_copy(descs.data(), nprob, table, s);
-  if (e != hipSuccess) return hip_fail(e, "problem table copy");
-  e = amk::launch_fused(descs[0], table, nprob, blocks, h0->f64, h0->shape.nv, max_m, s, lds, h0->tile, h0->waves);
+  constexpr int kChunk = 6;
+  Desc chunk[kChunk];
+  Desc first{};
+  int blk = 0;
+  for (int base = 0; base < nprob; base += kChunk) {
+    const int cnt = std::min(kChunk, nprob - base);
+    for (int k = 0; k < cnt; ++k) {
+      const int p = base + k;
+      chunk[k] = make_desc(handles[p], &problems[p], batch[p], iters[p], &states[p], h0->tile);
+      chunk[k].blk0 = blk;
+      blk += chunk[k].nblk;
+      if (p == 0) first = chunk[k];
+    }
+    hipError_t e = amk::launch_desc_copy(chunk, cnt, table + base, s);
+    if (e != hipSuccess) return hip_fail(e, "problem table copy");
+  }
+  hipError_t e = amk::launch_fused(first, table, nprob, blocks, h0->f64, h0->shape.nv, max_m, s, lds, h0->tile,
+                                   h0->waves);
   if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
   return AM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int am_solve_multi(int32_t nprob, am_handle *const *handles, const am_problem *problems, const int32_t *batch,
+                   const int32_t *iters, const am_state *states, void *workspace, size_t workspace_bytes,
+                   void *stream) {
+  if (nprob < 0 || nprob > amk::kMaxProblems)
+    return fail(AM_ERR_INVALID, "nprob must be in [0, %d]", amk::kMaxProblems);
+  if (nprob == 0) return AM_OK;
+  size_t need = 0;
+  am_multi_workspace_size(nprob, &need);
+  if (!workspace || workspace_bytes < need)
+    return fail(AM_ERR_INVALID, "workspace of %zu bytes needed", need);
+  return solve_multi_into(nprob, handles, problems, batch, iters, states, static_cast<Desc *>(workspace),
+                          amk::kMaxProblems, stream);
+}
+
+int am_solve_multi_static(int32_t nprob, am_handle *const *handles, const am_problem *problems, const int32_t *batch,
+                          const int32_t *iters, const am_state *states, void *stream) {
+  if (nprob < 0 || nprob > AM_STATIC_MAX_PROBLEMS)
+    return fail(AM_ERR_INVALID, "nprob must be in [0, %d] (AM_STATIC_MAX_PROBLEMS)", AM_STATIC_MAX_PROBLEMS);
+  if (nprob == 0) return AM_OK;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  Desc *table = nullptr;
+  if ((e = amk::static_table(dev, &table)) != hipSuccess) return hip_fail(e, "static problem table");
+  return solve_multi_into(nprob, handles, problems, batch, iters, states, table, AM_STATIC_MAX_PROBLEMS, stream);
 }
 
 int am_residuals(am_handle *h, const am_problem *p, int32_t batch, const am_state *st, void *out, void *stream) {

@@ -80,6 +80,10 @@ hipError_t launch_select_best(const void *res, int B, double tol, int32_t *idx, 
 hipError_t launch_residuals(const Desc &d, const void *P, const void *Pd, const void *Pdd, void *out,
                             bool f64, int nv, hipStream_t st);
 hipError_t launch_desc_copy(const Desc *host_descs, int count, Desc *dev_dst, hipStream_t st);
+// Device address of `device`'s copy of the static problem table
+// (AM_STATIC_MAX_PROBLEMS descriptors); `device` must be current on the
+// first call for it.
+hipError_t static_table(int device, Desc **out);
 hipError_t launch_plain(const Desc &d, void *ws, size_t ws_bytes, bool f64, int nv, hipStream_t st);
 size_t plain_workspace_bytes(int B, int q, int nv, int m, int n, bool f64);
 
