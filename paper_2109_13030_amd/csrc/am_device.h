@@ -148,11 +148,12 @@ struct FusedLds {
 
 // Per-wave vectors.  Position-block vectors hold one axis in 2nv contiguous
 // entries (x block then slack block), padded to a2 = pad4(2nv).  The
-// coefficients and the right-hand sides of the coefficient update are kept
-// in FP64 (zd, wd; dw elements of T per double), with a T copy of the
-// coefficients (z) for the evaluation of the derivative channels.
+// coefficients are kept in FP64 (zd; dw elements of T per double) with a T
+// copy (z) for the derivative channels; w and dz are the T operands of the
+// coefficient update's two products; wd stages the FP64 multipliers for
+// the write-back.
 struct WaveLds {
-  int z, zd, wd, zpsi, aux, red;
+  int z, w, dz, zd, wd, zpsi, aux, red;
 };
 
 __host__ __device__ constexpr int pad8(int v) { return (v + 7) & ~7; }
@@ -162,8 +163,10 @@ __host__ __device__ inline WaveLds wave_layout(int nv, int red_rows, int dw) {
   WaveLds w;
   int o = 0;
   w.z = o; o += pad8(2 * a2);           // T copy of z of (x, c) and (y, s)
+  w.w = o; o += pad8(2 * a2);           // lambda - rho F^T (F xi - g)
+  w.dz = o; o += pad8(2 * a2);          // the last update of z
   w.zd = o; o += pad8(2 * a2 * dw);     // z in FP64
-  w.wd = o; o += pad8(2 * a2 * dw);     // lambda - rho F^T (F xi - g) in FP64
+  w.wd = o; o += pad8(2 * a2 * dw);     // multipliers in FP64 (write-back)
   w.zpsi = o; o += pad8(p);             // heading coefficients
   w.aux = o; o += pad8(2 * a2 + p);     // set-up staging
   w.red = o; o += red_rows * kRedRowStride;

@@ -130,11 +130,28 @@ __device__ __forceinline__ T wave_sum_many(const T (&p)[G], T *red, int lane) {
   return s;
 }
 
-// Row I of a [2nv][2nv] operator stored as Quad [a2/4][2nv] times the FP64
-// 2nv-vector v (contiguous, 16-byte aligned, padded to a2), accumulated in
-// FP64.
+// Row I of a [2nv][2nv] operator stored as Quad [a2/4][2nv] times the
+// 2nv-vector v (contiguous, 16-byte aligned, padded to a2).
 template <typename T, int NV>
-__device__ __forceinline__ double row_dot(const T *op, int I, const double *v) {
+__device__ __forceinline__ T row_dot(const T *op, int I, const T *v) {
+  constexpr int N2 = 2 * NV, C = pad4(N2) / 4;
+  const Quad<T> *o = reinterpret_cast<const Quad<T> *>(op);
+  const Quad<T> *vv = reinterpret_cast<const Quad<T> *>(v);
+  T acc0 = T(0), acc1 = T(0);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const Quad<T> a = o[c * N2 + I], b = vv[c];
+    acc0 += a.a * b.a;
+    acc1 += a.b * b.b;
+    if (4 * c + 2 < N2) acc0 += a.c * b.c;
+    if (4 * c + 3 < N2) acc1 += a.d * b.d;
+  }
+  return acc0 + acc1;
+}
+
+// The same with an FP64 vector, accumulated in FP64.
+template <typename T, int NV>
+__device__ __forceinline__ double row_dot_d(const T *op, int I, const double *v) {
   constexpr int N2 = 2 * NV, C = pad4(N2) / 4;
   const Quad<T> *o = reinterpret_cast<const Quad<T> *>(op);
   const Pair<double> *vv = reinterpret_cast<const Pair<double> *>(v);
@@ -147,39 +164,6 @@ __device__ __forceinline__ double row_dot(const T *op, int I, const double *v) {
     acc1 += double(a.b) * b0.y;
     if (4 * c + 2 < N2) acc0 += double(a.c) * b1.x;
     if (4 * c + 3 < N2) acc1 += double(a.d) * b1.y;
-  }
-  return acc0 + acc1;
-}
-
-// Row I of a [2nv][2nv] operator in the Quad layout of row_dot, copied to
-// registers (zero past 2nv).
-template <typename T, int NV>
-__device__ __forceinline__ void row_load(const T *op, int I, T (&r)[pad4(2 * NV)]) {
-  constexpr int N2 = 2 * NV, C = pad4(N2) / 4;
-  const Quad<T> *o = reinterpret_cast<const Quad<T> *>(op);
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const Quad<T> a = o[c * N2 + I];
-    r[4 * c] = a.a;
-    r[4 * c + 1] = a.b;
-    r[4 * c + 2] = 4 * c + 2 < N2 ? a.c : T(0);
-    r[4 * c + 3] = 4 * c + 3 < N2 ? a.d : T(0);
-  }
-}
-
-// The same product with the row in registers.
-template <typename T, int NV>
-__device__ __forceinline__ double row_dot_reg(const T (&r)[pad4(2 * NV)], const double *v) {
-  constexpr int N2 = 2 * NV, C = pad4(N2) / 4;
-  const Pair<double> *vv = reinterpret_cast<const Pair<double> *>(v);
-  double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const Pair<double> b0 = vv[2 * c], b1 = vv[2 * c + 1];
-    acc0 += double(r[4 * c]) * b0.x;
-    acc1 += double(r[4 * c + 1]) * b0.y;
-    if (4 * c + 2 < N2) acc0 += double(r[4 * c + 2]) * b1.x;
-    if (4 * c + 3 < N2) acc1 += double(r[4 * c + 3]) * b1.y;
   }
   return acc0 + acc1;
 }
@@ -216,6 +200,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   const WaveLds wl = wave_layout(NV, RED, DW);
   T *wb = lds + L.wave0 + wave * L.wave_stride;
   T *vz = wb + wl.z, *vzpsi = wb + wl.zpsi, *vaux = wb + wl.aux;
+  T *vw = wb + wl.w, *vdz = wb + wl.dz;
   double *vzd = reinterpret_cast<double *>(wb + wl.zd), *vwd = reinterpret_cast<double *>(wb + wl.wd);
   T *red = wb + wl.red;
   // exchange area of this trajectory: [half][kXchHalf]
@@ -551,11 +536,14 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   eval_psi();
   psih = psi;
   // rows I of M1 and N (position block), read from LDS in every product
-  auto m1_dot = [&](const double *v) { return row_dot<T, NV>(M1, I, v); };
-  auto n_dot = [&](const double *v) { return row_dot<T, NV>(NQ, I, v); };
-  double nz = n_dot(vzd + axis * A2);   // row of N z
+  // (in registers they would push the kernel past its register budget)
+  auto m1_dot = [&](const T *v) { return row_dot<T, NV>(M1, I, v); };
+  auto n_dot = [&](const T *v) { return row_dot<T, NV>(NQ, I, v); };
+  // N z, formed once in FP64 and then carried: N z' = N z + N dz, the
+  // product of the small update in T
+  double nz = row_dot_d<T, NV>(NQ, I, vzd + axis * A2);
   project_reduce(false);
-  if (prow) vwd[axis * A2 + I] = lam - rhod * double(tr);
+  if (prow) vw[axis * A2 + I] = T(lam - rhod * double(tr));
   wave_sync();
 
   for (int it = 0; it < K; ++it) {
@@ -563,16 +551,18 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     // z' = z - H1 (A z - b) + M1 (lambda - rho F^T (F xi - g)) - N z
     // (every lane computes; lanes past the position rows compute a copy of
     // row 0 and store nothing)
-    zl += (m1_dot(vwd + axis * A2) - nz) - bcc;
+    const double dz = (double(m1_dot(vw + axis * A2)) - nz) - bcc;
     bcc = 0.0;
+    zl += dz;
     if (prow) {
       vzd[axis * A2 + I] = zl;
       vz[axis * A2 + I] = T(zl);
+      vdz[axis * A2 + I] = T(dz);
     }
     wave_sync();
     eval_xy();
     // N z of the new z, used by the next update
-    nz = n_dot(vzd + axis * A2);
+    nz += double(n_dot(vdz + axis * A2));
 
     // ---- xi2: psi_hat = atan2(s, c) on the branch nearest psi^k, then the
     // heading QP (eq. compute_convex_surrogate):
@@ -599,7 +589,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     project_reduce(true);
     if (prow) {
       lam -= rhod * double(tr);
-      vwd[axis * A2 + I] = lam - rhod * double(tr);
+      vw[axis * A2 + I] = T(lam - rhod * double(tr));
     }
     if (hrow) mu -= rhop * trpsi;
     wave_sync();
