@@ -63,7 +63,54 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def build_native() -> str:
+    """The same source built -O3 -march=native for timing on the host it runs
+    on (the CPU baseline); the library name carries a digest of the host's
+    CPU flags, so another host builds its own."""
+    import hashlib
+    flags = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("flags"):
+                flags = line
+                break
+    except OSError:
+        pass
+    tag = hashlib.sha256((flags + open(_SRC).read() + open(os.path.join(_HERE, "am_oracle.h")).read())
+                         .encode()).hexdigest()[:12]
+    path = os.path.join(_HERE, f"libamoracle_native_{tag}.so")
+    if not os.path.exists(path):
+        tmp = path + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, path)
+    return path
+
+
+NATIVE_FLAGS = "gcc -O3 -march=native -fopenmp"
 _lib = None
+_native = None
+
+
+def _bind(L):
+    L.amo_basis.argtypes = [ct.c_int, ct.c_int, ct.c_double, _dp, _dp, _dp]
+    L.amo_create.argtypes = [ct.POINTER(_Problem), ct.POINTER(ct.c_int)]
+    L.amo_create.restype = ct.c_void_p
+    L.amo_free.argtypes = [ct.c_void_p]
+    L.amo_matrices.argtypes = [ct.c_void_p, _dp, _dp, _dp]
+    L.amo_step.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.POINTER(_State)]
+    L.amo_solve.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.POINTER(_State), _dp, ct.c_int]
+    L.amo_lagrangian.argtypes = [ct.c_void_p, ct.c_int, ct.POINTER(_State), _dp]
+    L.amo_residuals.argtypes = [ct.c_void_p, ct.c_int, ct.POINTER(_State), _dp]
+    return L
+
+
+def native_lib():
+    """The -O3 -march=native build (timing only)."""
+    global _native
+    if _native is None:
+        _native = _bind(ct.CDLL(build_native()))
+    return _native
 
 
 def lib():
@@ -71,16 +118,7 @@ def lib():
     if _lib is None:
         build()
         L = ct.CDLL(_LIB)
-        L.amo_basis.argtypes = [ct.c_int, ct.c_int, ct.c_double, _dp, _dp, _dp]
-        L.amo_create.argtypes = [ct.POINTER(_Problem), ct.POINTER(ct.c_int)]
-        L.amo_create.restype = ct.c_void_p
-        L.amo_free.argtypes = [ct.c_void_p]
-        L.amo_matrices.argtypes = [ct.c_void_p, _dp, _dp, _dp]
-        L.amo_step.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.POINTER(_State)]
-        L.amo_solve.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.POINTER(_State), _dp, ct.c_int]
-        L.amo_lagrangian.argtypes = [ct.c_void_p, ct.c_int, ct.POINTER(_State), _dp]
-        L.amo_residuals.argtypes = [ct.c_void_p, ct.c_int, ct.POINTER(_State), _dp]
-        _lib = L
+        _lib = _bind(L)
     return _lib
 
 
@@ -123,10 +161,12 @@ def state_from(pb: dict, init: dict) -> dict:
 
 
 class Oracle:
-    """One problem (shared by the batch): setup matrices and LU factors."""
+    """One problem (shared by the batch): setup matrices and LU factors.
+    native=True uses the -O3 -march=native build (for timing)."""
 
-    def __init__(self, pb: dict):
+    def __init__(self, pb: dict, native: bool = False):
         self.pb = pb
+        self._L = native_lib() if native else lib()
         q, nv = int(pb["q"]), int(pb["nv"])
         self.q, self.nv = q, nv
         self.m, self.n = len(pb["r"]), len(pb["oa"])
@@ -150,13 +190,13 @@ class Oracle:
         p.flags = int(pb.get("flags", 0))
         self._p = p
         status = ct.c_int(0)
-        self._ctx = lib().amo_create(ct.byref(p), ct.byref(status))
+        self._ctx = self._L.amo_create(ct.byref(p), ct.byref(status))
         if not self._ctx:
             raise ValueError(f"oracle setup failed with status {status.value}")
 
     def __del__(self):
         if getattr(self, "_ctx", None):
-            lib().amo_free(self._ctx)
+            self._L.amo_free(self._ctx)
             self._ctx = None
 
     def _st(self, st: dict):
@@ -179,19 +219,19 @@ class Oracle:
         F = np.zeros((nF, 2 * self.nv))
         K1 = np.zeros((2 * self.nv + 6, 2 * self.nv + 6))
         K2 = np.zeros((self.nv + 6, self.nv + 6))
-        lib().amo_matrices(self._ctx, _ptr(F), _ptr(K1), _ptr(K2))
+        self._L.amo_matrices(self._ctx, _ptr(F), _ptr(K1), _ptr(K2))
         return F, K1, K2
 
     def step(self, which: int, st: dict):
         s, B = self._st(st)
-        rc = lib().amo_step(self._ctx, B, which, ct.byref(s))
+        rc = self._L.amo_step(self._ctx, B, which, ct.byref(s))
         if rc != 0:
             raise RuntimeError(f"amo_step failed: {rc}")
 
     def solve(self, st: dict, K: int, hist: bool = False, nthreads: int = 0):
         s, B = self._st(st)
         h = np.zeros((max(K, 1), B)) if hist else None
-        rc = lib().amo_solve(self._ctx, B, K, ct.byref(s), _ptr(h) if hist else None, nthreads)
+        rc = self._L.amo_solve(self._ctx, B, K, ct.byref(s), _ptr(h) if hist else None, nthreads)
         if rc != 0:
             raise RuntimeError(f"amo_solve failed: {rc}")
         return h[:K] if hist else None
@@ -199,13 +239,13 @@ class Oracle:
     def lagrangian(self, st: dict):
         s, B = self._st(st)
         out = np.zeros(B)
-        lib().amo_lagrangian(self._ctx, B, ct.byref(s), _ptr(out))
+        self._L.amo_lagrangian(self._ctx, B, ct.byref(s), _ptr(out))
         return out
 
     def residuals(self, st: dict):
         s, B = self._st(st)
         out = np.zeros((B, NRES))
-        lib().amo_residuals(self._ctx, B, ct.byref(s), _ptr(out))
+        self._L.amo_residuals(self._ctx, B, ct.byref(s), _ptr(out))
         return out
 
     def trajectories(self, st: dict):

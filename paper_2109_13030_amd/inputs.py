@@ -226,6 +226,19 @@ def replan_problem(pb: dict, step: int, period: float = 0.04) -> dict:
     return dict(pb, ox=ox + vx[:, None] * shift, oy=oy + vy[:, None] * shift)
 
 
+def as_stored(pb: dict, init: dict, dtype: str):
+    """The problem and initial state as device arrays of `dtype` hold them:
+    for FP32 the obstacle table and the initial coefficients and
+    multipliers rounded once to float32 (the problem's scalars travel as
+    doubles through the C-ABI and are unchanged)."""
+    if dtype != "f32":
+        return pb, init
+    r32 = lambda v: np.asarray(np.asarray(v, np.float64), np.float32).astype(np.float64)
+    pb = dict(pb, **{k: r32(pb[k]) for k in ("ox", "oy", "oa", "ob")})
+    init = {k: r32(v) for k, v in init.items()}
+    return pb, init
+
+
 def poisson_arrivals(rate_hz: float, count: int, seed: int = 0) -> np.ndarray:
     """Arrival times [s] of a Poisson process of the given rate."""
     rng = np.random.default_rng(seed)

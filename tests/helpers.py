@@ -5,6 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
+from paper_2109_13030_amd import inputs
 
 # FP32 parity tolerance of the fixed-iteration solve against the FP64 oracle
 TOL_POS = 1e-3   # m
@@ -13,17 +14,10 @@ TOL_PSI = 1e-3   # rad
 
 def as_stored(pb: dict, init: dict, dtype: str):
     """The problem and initial state as the device arrays of `dtype` hold
-    them: for FP32 the obstacle table and the initial coefficients and
-    multipliers rounded once to float32 (the scalars of the problem travel
-    as doubles through the C-ABI).  The oracle is run on these values, so
-    that a parity test measures the arithmetic of the path and not the
-    quantisation of its inputs."""
-    if dtype != "f32":
-        return pb, init
-    r32 = lambda v: np.asarray(np.asarray(v, np.float64), np.float32).astype(np.float64)
-    pb = dict(pb, **{k: r32(pb[k]) for k in ("ox", "oy", "oa", "ob")})
-    init = {k: r32(v) for k, v in init.items()}
-    return pb, init
+    them (inputs.as_stored).  The oracle of an FP32 test runs on these
+    values, so that a parity test measures the arithmetic of the path and
+    not the quantisation of its inputs."""
+    return inputs.as_stored(pb, init, dtype)
 
 
 def subset(init: dict, idx) -> dict:
