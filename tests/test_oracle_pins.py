@@ -632,3 +632,63 @@ def test_fp32_input_rounding_is_amplified():
     x32, y32, _ = orc32.trajectories(st32)
     move = max(np.abs(x - x32).max(), np.abs(y - y32).max())
     assert move > 1e-3, move
+
+
+def test_residual_heading_clearance_acceleration_and_flag_columns():
+    """Residual columns 5, 8, 10 and 11 against their definitions written
+    independently: the heading gap of the slack pair to psi (eqs. cos_ref,
+    sin_ref) as the unsigned angle between the unit vectors (c, s)/|(c, s)|
+    and (cos psi, sin psi), so the 2 pi wrap is never formed; the clearance
+    level of eq. collision_avoidance_proposed as the radius of each circle
+    centre over the polar radius of its grown ellipse in the same direction,
+    minus one; the acceleration bound of eq. acc_constraint from SciPy's
+    second-derivative basis; the non-finite flag from numpy's isfinite."""
+    pb = tiny_problem()
+    ref = PaperProblem(pb)
+    st = random_state(pb, 4, seed=61)
+    st["cpsi"] *= 12.0          # headings of several radians: the gap wraps
+    res = oracle.Oracle(pb).residuals(st)
+    q = ref.q
+    for l in range(4):
+        c, s, psi = ref.P @ st["cc"][l], ref.P @ st["cs"][l], ref.P @ st["cpsi"][l]
+        gap = np.arccos(np.clip((c * np.cos(psi) + s * np.sin(psi)) / np.hypot(c, s), -1.0, 1.0))
+        assert np.abs(atan2z(s, c) - psi).max() > np.pi   # the wrap is exercised
+        np.testing.assert_allclose(res[l, 5], gap.max(), rtol=1e-9, atol=1e-12)
+        level = np.inf
+        for i in range(ref.m):
+            for j in range(ref.n):
+                xt = ref.P @ st["cx"][l] + ref.r[i] * np.cos(psi) - ref.ox[j]
+                yt = ref.P @ st["cy"][l] + ref.r[i] * np.sin(psi) - ref.oy[j]
+                th = np.arctan2(yt, xt)
+                rb = ref.a[j] * ref.b[j] / np.hypot(ref.b[j] * np.cos(th), ref.a[j] * np.sin(th))
+                level = min(level, (np.hypot(xt, yt) / rb - 1.0).min())
+        np.testing.assert_allclose(res[l, 8], level, rtol=1e-10, atol=1e-12)
+        acc = np.hypot(ref.Pdd @ st["cx"][l], ref.Pdd @ st["cy"][l])
+        np.testing.assert_allclose(res[l, 10], (acc - pb["amax"]).max(), rtol=1e-10, atol=1e-14)
+        assert res[l, 11] == 0.0
+    # one non-finite value in one array of one trajectory flags that one only
+    for key, l in (("lam", 1), ("alpha", 2), ("cpsi", 3), ("d", 0)):
+        bad = {k: v.copy() for k, v in st.items()}
+        bad[key][l].flat[1] = np.nan if key != "d" else np.inf
+        flags = oracle.Oracle(pb).residuals(bad)[:, 11]
+        expect = np.array([0.0 if all(np.isfinite(bad[k][i]).all() for k in bad) else 1.0 for i in range(4)])
+        np.testing.assert_array_equal(flags, expect)
+        assert flags[l] == 1.0 and flags.sum() == 1.0
+
+
+def test_lagrangian_follows_its_definition():
+    """amo_lagrangian against eq. reform_bergman written row by row: the xi1
+    objective of tests/paper_ref.py (the smoothness term, -<lambda, xi1> and
+    rho/2 |F xi1 - g|^2 from the constraint rows of Sec. III-C) plus
+    1/2 |Pddot c_psi|^2 - <lambda_psi, c_psi>, under both readings of the
+    smoothness blocks."""
+    for flags in (0, oracle.Q_CS_ZERO):
+        pb = tiny_problem(flags=flags)
+        ref = PaperProblem(pb)
+        st = random_state(pb, 3, seed=71)
+        L = oracle.Oracle(pb).lagrangian(st)
+        for l in range(3):
+            xi1 = np.concatenate([st["cx"][l], st["cc"][l], st["cy"][l], st["cs"][l]])
+            want = ref.xi1_objective(st, l)(xi1)
+            want += 0.5 * np.sum((ref.Pdd @ st["cpsi"][l]) ** 2) - st["lampsi"][l] @ st["cpsi"][l]
+            np.testing.assert_allclose(L[l], want, rtol=1e-11)
