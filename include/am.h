@@ -46,7 +46,8 @@ extern "C" {
 #define AM_ERR_INVALID   (-1)  /* bad argument (nothing launched)            */
 #define AM_ERR_HIP       (-2)  /* a HIP runtime call failed                   */
 #define AM_ERR_SINGULAR  (-4)  /* a KKT matrix is numerically singular        */
-#define AM_ERR_NONFINITE (-5)  /* residuals found NaN/Inf in a trajectory     */
+#define AM_ERR_NONFINITE (-5)  /* every trajectory of a served request is
+                                  NaN/Inf (am_server_best)                    */
 #define AM_ERR_NOMEM     (-6)  /* device allocation failed (am_setup only)    */
 
 /* element types */
@@ -68,12 +69,10 @@ extern "C" {
  * AM_Q_CS_ZERO      acceleration cost on the x, y blocks of xi1 only; default:
  *                   on all four blocks (Sec. III-C, "block-diagonal stacking").
  * Precision option (not a reading; AM_F32 handles only):
- * AM_PLAIN_BF16X3   the plain path forms its two dense contractions on the
- *                   matrix cores: the stacked F^T(F xi - g) with BF16
- *                   products, FP32 accumulation and a split correction
- *                   (a_hi b_hi + a_hi b_lo + a_lo b_hi), and the xi1
- *                   product KKT^-1 rhs (eq. zeta_1_sepration_3) with FP32
- *                   matrix-core products. */
+ * AM_PLAIN_BF16X3   the plain path forms the stacked contraction
+ *                   F^T(F xi - g) of eq. (zeta_1_sepration_3) on the matrix
+ *                   cores: BF16 products, FP32 accumulation and a split
+ *                   correction (a_hi b_hi + a_hi b_lo + a_lo b_hi). */
 #define AM_ALPHA_LITERAL  1u
 #define AM_XTILDE_SLACK   2u
 #define AM_PSI_NO_UNWRAP  4u
@@ -333,9 +332,10 @@ int am_server_submit(am_server *s, const am_request *r, int64_t *ticket);
 int am_server_wait(am_server *s, int64_t ticket, double timeout_s, int32_t *done, double *latency_s,
                    void *traj);
 /* Best trajectory of a finished request (server created with select_best):
- * its index in the request's batch (-1 if every trajectory is non-finite),
- * its cost and its max |f_c| (either may be NULL).  AM_ERR_INVALID if the
- * request has not finished. */
+ * its index in the request's batch, its cost and its max |f_c| (either may
+ * be NULL).  If every trajectory is non-finite, *index = -1 and the call
+ * returns AM_ERR_NONFINITE.  AM_ERR_INVALID if the request has not
+ * finished. */
 int am_server_best(am_server *s, int64_t ticket, int32_t *index, double *cost, double *fc_max);
 /* Counters: requests completed, launches issued, peak bytes of the budget
  * in use, requests that waited for memory (any may be NULL). */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "am_internal.h"
+#include "am_poly.h"
 
 namespace amk {
 
@@ -12,49 +13,43 @@ struct Num;
 
 // FP32 atan2 and sincos written for the iteration kernels (fewer
 // instructions than the general library routines, which also handle huge
-// arguments).  Both use polynomial fits made for this library by iteratively
-// reweighted least squares (a near-minimax fit) on dense grids:
+// arguments).  The coefficients (am_poly.h) are near-minimax fits made by
+// paper_2109_13030_amd/gen_poly.py (Lawson's iteratively reweighted least
+// squares on dense grids, rounded to FP32):
 //  * atan(r) = r P(r^2) on [0, 1], P of degree 8, then the octant fix-ups
-//    atan2 = pi/2 - atan(1/r), pi - ... and the sign of y; max error
-//    ~3e-7 rad including the rounding of min/max;
+//    atan2 = pi/2 - atan(1/r), pi - ... and the sign of y; within 3.2e-7 rad
+//    with an exact reciprocal, 3.7e-7 rad with the hardware reciprocal's
+//    one unit in the last place;
 //  * sin r = r + r^3 S(r^2), cos r = 1 - r^2/2 + r^4 C(r^2) on [-pi/4, pi/4],
 //    S and C of degree 3, after a two-constant Cody-Waite reduction by
-//    pi/2 with fused multiply-adds (exact for |a| < ~1e4 to ~1e-11);
-//    max error ~9e-8.
+//    pi/2 with fused multiply-adds; within 1e-7 for |a| <= 1e3.
+// tests/test_poly.py checks both bounds with an FP32 emulation.
 // The zero vector is handled by atan2z, not here.
 __device__ __forceinline__ float atan2_f32(float y, float x) {
   const float ax = fabsf(x), ay = fabsf(y);
   const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
   const float r = mn * __builtin_amdgcn_rcpf(mx), u = r * r;
-  float p = 0.002452445449307561f;
-  p = fmaf(p, u, -0.014384330250322819f);
-  p = fmaf(p, u, 0.03975366801023483f);
-  p = fmaf(p, u, -0.07232531905174255f);
-  p = fmaf(p, u, 0.10497856885194778f);
-  p = fmaf(p, u, -0.14160951972007751f);
-  p = fmaf(p, u, 0.19985872507095337f);
-  p = fmaf(p, u, -0.33332595229148865f);
-  p = fmaf(p, u, 0.9999998807907104f);
+  float p = kAtanP[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) p = fmaf(p, u, kAtanP[i]);
   float a = r * p;
-  a = ay > ax ? 1.5707963267948966f - a : a;
-  a = x < 0.0f ? 3.141592653589793f - a : a;
+  a = ay > ax ? kHalfPi - a : a;
+  a = x < 0.0f ? kPi - a : a;
   return copysignf(a, y);
 }
 
 __device__ __forceinline__ void sincos_f32(float a, float *s, float *c) {
-  const float k = rintf(a * 0.6366197723675814f);           // nearest multiple of pi/2
-  float r = fmaf(-k, 1.5707963705062866f, a);               // pi/2 = c1 + c2
-  r = fmaf(-k, -4.371138828673793e-08f, r);
+  const float k = rintf(a * kTwoOverPi);                     // nearest multiple of pi/2
+  float r = fmaf(-k, kHalfPiHi, a);                          // pi/2 = hi + lo
+  r = fmaf(-k, kHalfPiLo, r);
   const float u = r * r;
-  float ps = 2.716131348279305e-06f;
-  ps = fmaf(ps, u, -0.00019839058222714812f);
-  ps = fmaf(ps, u, 0.008333328180015087f);
-  ps = fmaf(ps, u, -0.1666666716337204f);
+  float ps = kSinS[0];
+#pragma unroll
+  for (int i = 1; i < 4; ++i) ps = fmaf(ps, u, kSinS[i]);
   const float sr = fmaf(r * u, ps, r);
-  float pc = -2.721033922625793e-07f;
-  pc = fmaf(pc, u, 2.479952308931388e-05f);
-  pc = fmaf(pc, u, -0.0013888883404433727f);
-  pc = fmaf(pc, u, 0.0416666679084301f);
+  float pc = kCosC[0];
+#pragma unroll
+  for (int i = 1; i < 4; ++i) pc = fmaf(pc, u, kCosC[i]);
   const float cr = fmaf(u * u, pc, fmaf(-0.5f, u, 1.0f));
   const int qd = int(k) & 3;                                 // quadrant of a
   const float s0 = (qd & 1) ? cr : sr, c0 = (qd & 1) ? sr : cr;

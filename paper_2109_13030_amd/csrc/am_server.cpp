@@ -86,7 +86,7 @@ class Arena {
 struct Block {      // one arena allocation
   size_t off = 0, bytes = 0;
   bool live = false;
-  int B = 0;        // trajectories (warm blocks)
+  int B = 0, nv = 0, q = 0;  // layout of a warm block's state
   uint64_t used = 0;  // last use (warm blocks, LRU)
 };
 
@@ -99,6 +99,7 @@ struct Request {
   Clock::time_point t_submit, t_done;
   bool done = false;
   int status = AM_OK;
+  std::string error;               // message of a failed launch
   Block state, table, work;        // state + trajectories, obstacle table, plain workspace
   Block warm_src;                  // the client's warm block used at admission (if any)
   char *best_host = nullptr;       // pinned copy of (cost, max |f_c|, index) of the best trajectory
@@ -206,12 +207,17 @@ bool am_server::alloc_evicting(size_t bytes, int keep_client, size_t *off) {
 }
 
 bool am_server::admit(Slot &slot, std::vector<Request *> &batch) {
-  // called with mu held; arrival order, a client's requests one at a time
+  // called with mu held; arrival order, a client's requests one at a time.
+  // One launch holds requests of one (q, nv) (the multi-problem launch's
+  // condition): the first admissible request fixes them, and requests of
+  // another (q, nv) keep their place for a later launch.
   const int cap = cfg.mode == AM_SERVE_CONTINUOUS ? cfg.max_per_launch : 1;
   const size_t es = elem_size(cfg.dtype);
+  int q0 = -1, nv0 = -1;
   for (auto it = pending.begin(); it != pending.end() && int(batch.size()) < cap;) {
     Request *r = *it;
     if (client_busy.count(r->client)) { ++it; continue; }
+    if (q0 >= 0 && (r->q != q0 || r->nv != nv0)) { ++it; continue; }
     const size_t sb = state_elems(r->B, r->nv, r->q) * es, tb = table_elems(r->n, r->q) * es;
     size_t wb = 0;
     if (cfg.mode == AM_SERVE_PLAIN) am_plain_workspace_size(r->h, r->B, &wb);
@@ -227,8 +233,12 @@ bool am_server::admit(Slot &slot, std::vector<Request *> &batch) {
     }
     r->state = st; r->table = tab; r->work = wk;
     r->warm_src = Block{};
+    q0 = r->q;
+    nv0 = r->nv;
+    // the client's last result seeds the multipliers when its layout matches
+    // this request's (same batch, coefficients and time steps)
     auto wit = warm.find(r->client);
-    if (wit != warm.end() && wit->second.B == r->B) {
+    if (wit != warm.end() && wit->second.B == r->B && wit->second.nv == r->nv && wit->second.q == r->q) {
       wit->second.used = ++clock;
       r->warm_src = wit->second;
     }
@@ -354,12 +364,19 @@ void am_server::retire(Slot &slot) {
                        : double(reinterpret_cast<const float *>(r->best_host)[1]);
     }
     r->best_host = nullptr;
-    auto wit = warm.find(r->client);
-    if (wit != warm.end()) arena.release(wit->second.off, wit->second.bytes);
-    Block w = r->state;                    // the result seeds the client's next request
-    w.B = r->B;
-    w.used = ++clock;
-    warm[r->client] = w;
+    if (r->status == AM_OK) {
+      auto wit = warm.find(r->client);
+      if (wit != warm.end()) arena.release(wit->second.off, wit->second.bytes);
+      Block w = r->state;                  // the result seeds the client's next request
+      w.B = r->B;
+      w.nv = r->nv;
+      w.q = r->q;
+      w.used = ++clock;
+      warm[r->client] = w;
+    } else {
+      // a failed launch leaves no result: the client keeps its previous warm block
+      arena.release(r->state.off, r->state.bytes);
+    }
     arena.release(r->table.off, r->table.bytes);
     if (r->work.live) arena.release(r->work.off, r->work.bytes);
     client_busy.erase(r->client);
@@ -390,9 +407,14 @@ void am_server::run() {
       const int rc = launch(s);
       lk.lock();
       if (rc != AM_OK) {
-        // a failed launch completes its requests with the error
+        // a failed launch completes its requests with the error (and the
+        // message this thread recorded)
+        const std::string msg = am_last_error();
         (void)hipStreamSynchronize(s.stream);
-        for (Request *r : s.reqs) r->status = rc;
+        for (Request *r : s.reqs) {
+          r->status = rc;
+          r->error = msg;
+        }
         retire(s);
         cv_done.notify_all();
       }
@@ -538,7 +560,7 @@ int am_server_wait(am_server *s, int64_t ticket, double timeout_s, int32_t *done
   else s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred);
   *done = r->done ? 1 : 0;
   if (!r->done) return AM_OK;
-  if (r->status != AM_OK) return srv_fail(r->status, "request failed on the device");
+  if (r->status != AM_OK) return srv_fail(r->status, "request failed on the device: " + r->error);
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
   if (traj) {
     // the result lives in the client's warm slot until the client's next
@@ -562,10 +584,11 @@ int am_server_best(am_server *s, int64_t ticket, int32_t *index, double *cost, d
   if (it == s->all.end()) return srv_fail(AM_ERR_INVALID, "unknown ticket");
   const Request *r = it->second.get();
   if (!r->done) return srv_fail(AM_ERR_INVALID, "request " + std::to_string(ticket) + " is not finished");
-  if (r->status != AM_OK) return srv_fail(r->status, "request failed on the device");
+  if (r->status != AM_OK) return srv_fail(r->status, "request failed on the device: " + r->error);
   *index = r->best;
   if (cost) *cost = r->best_cost;
   if (fc_max) *fc_max = r->best_fc;
+  if (r->best < 0) return srv_fail(AM_ERR_NONFINITE, "every trajectory of the request is non-finite");
   return AM_OK;
 }
 

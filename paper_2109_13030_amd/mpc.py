@@ -126,9 +126,11 @@ class MPC:
                  circles: int = 5, length: float = 1.5, width: float = 0.5, n_obs: int = 10,
                  vmax: float = 1.5, amax: float = 1.5, rho: float = 1.0, sigma: float = 0.5,
                  fc_tol: float = 0.02, buffer: float = 0.05, reuse_previous: bool = True,
-                 dt: float = 0.04, seed: int = 0):
+                 dt: float = 0.04, seed: int = 0, dtype: str = "f32"):
         import torch
         self.torch = torch
+        self.dtype = dtype
+        self.history = []   # per period: (selected index, its coefficients)
         self.B, self.K, self.tf, self.q, self.nv = int(batch), int(iters), float(horizon), int(q), int(nv)
         self.m, self.n = int(circles), int(n_obs)
         self.length, self.width = float(length), float(width)
@@ -139,10 +141,11 @@ class MPC:
         self.vmax, self.amax, self.rho, self.sigma, self.fc_tol = vmax, amax, rho, sigma, fc_tol
         self.buffer, self.reuse, self.dt = float(buffer), bool(reuse_previous), float(dt)
         self.rng = np.random.default_rng(seed)
-        self.h = am.Handle(self.q, self.nv, self.tf, self.r, self.n, self.rho, dtype="f32")
+        self.h = am.Handle(self.q, self.nv, self.tf, self.r, self.n, self.rho, dtype=dtype)
         self.state = None
         self.prev = None
-        self.res = torch.empty((self.B, am.NRES), dtype=torch.float32, device="cuda")
+        self.res = torch.empty((self.B, am.NRES), dtype=torch.float32 if dtype == "f32" else torch.float64,
+                               device="cuda")
         # coefficients of a trajectory delayed by one period, by least squares
         # on the grid: c' = pinv(P) P(t + dt) c
         grid = inputs.time_grid(self.q, self.tf)
@@ -206,16 +209,14 @@ class MPC:
                 init[k][0] = self.shift @ self.prev[k]
         return init
 
-    def plan(self, pb: dict):
-        """One replanning period: solve, select; returns (coefficients of the
-        best trajectory (x, y, psi), whether it met the collision tolerance,
-        milliseconds from upload to selection)."""
-        torch = self.torch
-        t0 = time.perf_counter()
-        p = am.DeviceProblem(pb, "f32")
-        init = self.samples(pb)
+    def solve_select(self, pb: dict, init: dict):
+        """The batch solve of one period on the GPU, from the given samples
+        and the multipliers kept from the previous period, then the residuals
+        and the best-trajectory selection; returns (index, its coefficients,
+        its max |f_c|)."""
+        p = am.DeviceProblem(pb, self.dtype)
         if self.state is None:
-            self.state = am.DeviceState(init, self.m, self.n, self.q, "f32", outputs=False)
+            self.state = am.DeviceState(init, self.m, self.n, self.q, self.dtype, outputs=False)
         else:
             self.state.load_coefficients(init)   # multipliers stay: warm start
         am.solve(self.h, p, self.state, self.K)
@@ -224,7 +225,17 @@ class MPC:
         if idx < 0:
             raise RuntimeError("every trajectory of the batch is non-finite")
         coef = {k: self.state.t[k][idx].double().cpu().numpy() for k in ("cx", "cc", "cy", "cs", "cpsi")}
+        return idx, coef, fc
+
+    def plan(self, pb: dict):
+        """One replanning period: solve, select; returns (coefficients of the
+        best trajectory (x, y, psi), whether it met the collision tolerance,
+        milliseconds from upload to selection)."""
+        t0 = time.perf_counter()
+        init = self.samples(pb)
+        idx, coef, fc = self.solve_select(pb, init)
         self.prev = coef
+        self.history.append((idx, coef))
         ms = (time.perf_counter() - t0) * 1e3
         return coef, fc <= self.fc_tol, ms
 
@@ -235,6 +246,7 @@ class MPC:
         every period with the true rectangle and discs."""
         self.state = None
         self.prev = None
+        self.history = []
         dt = self.dt
         p = crowd.start.astype(float).copy()
         v = np.array([crowd.speed, 0.0])

@@ -193,6 +193,18 @@ def test_largest_sizes_plain_f64():
     _compare_f64(pb, init, 4, plain=True)
 
 
+def test_singular_kkt_is_reported():
+    """A valid shape whose xi1 KKT matrix is numerically singular: a horizon of
+    1 ms makes the acceleration blocks ~1e22 times the position blocks, so
+    Gauss-Jordan meets a pivot below 1e-13 of the largest entry; am_setup
+    returns AM_ERR_SINGULAR and no handle."""
+    from paper_2109_13030_amd import am
+    pb, _ = inputs.workload("c1", batch=1)
+    with pytest.raises(am.AmError) as e:
+        am.Handle.for_problem(dict(pb, tf=1e-3), "f64")
+    assert e.value.code == am.AM_ERR_SINGULAR, str(e.value)
+
+
 def test_largest_sizes_f64_fit_or_clean_error():
     """FP64 at the largest sizes needs more LDS than a workgroup may hold: the
     solve either matches the oracle or is refused before any launch with a
@@ -303,6 +315,44 @@ def test_multi_problem_launch_equals_single_launches():
     for s, s1 in zip(sts, singles):
         for k in ("cx", "cy", "cpsi", "lam", "lam_psi", "traj"):
             assert torch.equal(s.t[k], s1.t[k]), k
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_multi_problem_launch_matches_oracle(dtype):
+    """One multi-problem launch over problems of different circle and
+    obstacle counts and batch sizes (each with its own KKT, eq. over_3), run
+    eagerly and as a replayed HIP graph, against the oracle problem by
+    problem: FP64 within 1e-8, FP32 within the 1e-3 tolerance."""
+    import torch
+    from paper_2109_13030_amd import am
+    probs = inputs.uneven_problems("c3", count=6, batch_cap=12)
+    assert len({len(pb["r"]) for pb, _ in probs}) > 1 and len({len(pb["oa"]) for pb, _ in probs}) > 1
+    K = 30 if dtype == "f64" else 100
+    hs = [am.Handle.for_problem(pb, dtype) for pb, _ in probs]
+    dps = [am.DeviceProblem(pb, dtype) for pb, _ in probs]
+    mk = lambda: [am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], dtype) for pb, init in probs]
+    ws = torch.empty(am.multi_workspace_size(len(probs)), dtype=torch.uint8, device="cuda")
+    eager = mk()
+    am.solve_multi(hs, dps, eager, K, ws)
+    torch.cuda.synchronize()
+    pristine, work = mk(), mk()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        am.solve_multi(hs, dps, work, K, ws)
+    for s, p in zip(work, pristine):
+        for k in am.DeviceState.KEYS:
+            s.t[k].copy_(p.t[k])
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for (pb, init), e, w in zip(probs, eager, work):
+        for out in (e.numpy(), w.numpy()):
+            if dtype == "f64":
+                orc, ost = H.run_oracle(pb, init, K)
+                epos, epsi = H.traj_errors(pb, out, orc, ost)
+                assert epos.max() < 1e-8 and epsi.max() < 1e-8, (epos.max(), epsi.max())
+            else:
+                _fp32_gate(pb, init, K, None, out)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])

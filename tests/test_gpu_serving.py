@@ -32,8 +32,10 @@ def _handles(am, clients):
 
 
 def test_same_result_alone_and_in_the_mix(am):
-    """A request's trajectories are bit-identical whether it runs alone or
-    batched with others that arrive at the same time."""
+    """A request's trajectories are bit-identical whether it runs alone or in
+    one launch with others.  The mix is made to share a launch: one stream,
+    and a long request occupies it while the eight arrive, so the scheduler
+    admits all eight together once the stream frees (launches < requests)."""
     clients = _clients(8)
     hs = _handles(am, clients)
     K = 12
@@ -42,14 +44,18 @@ def test_same_result_alone_and_in_the_mix(am):
     done, _, alone = s1.wait(t, 60.0, traj=True)
     assert done
     s1.close()
-    # the mix on a server that polls between arrivals (idle-spin window)
-    s2 = am.Server(1 << 28, streams=4, max_per_launch=16, idle_spin_us=5000)
+    s2 = am.Server(1 << 28, streams=1, max_per_launch=16, idle_spin_us=5000)
+    blocker = _clients(9)[8]
+    hb = _handles(am, [blocker])[0]
+    tb = s2.submit(hb, blocker["problem"], 100, blocker["batch"], 20000, blocker["init"])
     tickets = [s2.submit(h, c["problem"], i, c["batch"], K, c["init"]) for i, (h, c) in enumerate(zip(hs, clients))]
     outs = [s2.wait(tk, 60.0, traj=True) for tk in tickets]
+    assert s2.wait(tb, 60.0)[0]
     assert all(o[0] for o in outs)
     np.testing.assert_array_equal(outs[3][2], alone)
     st = s2.stats()
-    assert st["completed"] == len(clients)
+    assert st["completed"] == len(clients) + 1
+    assert st["launches"] < st["completed"], st
     s2.close()
     # and equal to the direct batch solve
     import torch
@@ -59,6 +65,97 @@ def test_same_result_alone_and_in_the_mix(am):
     am.solve(hs[3], p, ds, K)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(ds.t["traj"].cpu().numpy(), alone)
+
+
+def test_requests_of_two_shapes_in_one_queue(am):
+    """Requests of two time-step counts queued together while a long request
+    holds the only stream: each launch holds one shape (a launch mixing them
+    would be refused), every request completes, and each result equals its
+    direct solve."""
+    import dataclasses
+
+    import torch
+    cfg = dataclasses.replace(inputs.CONFIGS["c5"], q=64)
+    short = []
+    for k in range(3):
+        pb = inputs.make_problem(cfg, 500 + k, m=5, n=6 + k)
+        short.append(dict(problem=pb, init=inputs.make_initial(pb, 40, 600 + k), batch=40, n=6 + k))
+    mixed = [c for pair in zip(_clients(3, cap=40), short) for c in pair]
+    hs = _handles(am, mixed)
+    K = 9
+    s = am.Server(1 << 28, streams=1, max_per_launch=16, idle_spin_us=5000)
+    blocker = _clients(9)[8]
+    hb = _handles(am, [blocker])[0]   # the server uses the handle until the request completes
+    tb = s.submit(hb, blocker["problem"], 100, blocker["batch"], 20000, blocker["init"])
+    tickets = [s.submit(h, c["problem"], i, c["batch"], K, c["init"]) for i, (h, c) in enumerate(zip(hs, mixed))]
+    outs = [s.wait(tk, 60.0, traj=True) for tk in tickets]
+    assert s.wait(tb, 60.0)[0]
+    st = s.stats()
+    s.close()
+    assert all(o[0] for o in outs)
+    assert st["launches"] >= 3, st   # the blocker, then at least one launch per shape
+    for h, c, (_, _, traj) in zip(hs, mixed, outs):
+        p = am.DeviceProblem(c["problem"], "f32")
+        ds = am.DeviceState(c["init"], 5, c["n"], c["problem"]["q"], "f32")
+        am.solve(h, p, ds, K)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ds.t["traj"].cpu().numpy(), traj)
+
+
+def test_served_requests_match_the_oracle(am):
+    """FP64 server: a mix of requests and a warm-started second request of
+    one client, each against the FP64 oracle at 1e-8; the oracle's second
+    solve starts from fresh samples and the multipliers of its own first
+    solve (the warm start of Sec. IV)."""
+    import oracle
+    clients = _clients(3, cap=24)
+    hs = [am.Handle.for_problem(c["problem"], "f64") for c in clients]
+    K = 12
+    s = am.Server(1 << 28, streams=2, max_per_launch=8, dtype="f64")
+    tickets = [s.submit(h, c["problem"], i, c["batch"], K, c["init"]) for i, (h, c) in enumerate(zip(hs, clients))]
+    outs = [s.wait(tk, 60.0, traj=True) for tk in tickets]
+    c0 = clients[0]
+    pb2 = inputs.replan_problem(c0["problem"], 1)
+    init2 = inputs.make_initial(pb2, c0["batch"], 99)
+    t2 = s.submit(hs[0], pb2, 0, c0["batch"], K, init2)
+    warm = s.wait(t2, 60.0, traj=True)
+    s.close()
+    assert all(o[0] for o in outs) and warm[0]
+    first = None
+    for c, (_, _, traj) in zip(clients, outs):
+        orc = oracle.Oracle(c["problem"])
+        ost = oracle.state_from(c["problem"], c["init"])
+        orc.solve(ost, K)
+        x, y, p = orc.trajectories(ost)
+        np.testing.assert_allclose(traj[:, 0], x, atol=1e-8, rtol=0)
+        np.testing.assert_allclose(traj[:, 1], y, atol=1e-8, rtol=0)
+        np.testing.assert_allclose(traj[:, 2], p, atol=1e-8, rtol=0)
+        if first is None:
+            first = ost
+    orc = oracle.Oracle(pb2)
+    ost = oracle.state_from(pb2, dict(init2, lam=first["lam"], lampsi=first["lampsi"]))
+    orc.solve(ost, K)
+    x, y, p = orc.trajectories(ost)
+    np.testing.assert_allclose(warm[2][:, 0], x, atol=1e-8, rtol=0)
+    np.testing.assert_allclose(warm[2][:, 1], y, atol=1e-8, rtol=0)
+    np.testing.assert_allclose(warm[2][:, 2], p, atol=1e-8, rtol=0)
+
+
+def test_all_nonfinite_request_reports_nonfinite(am):
+    """A request whose every trajectory is NaN: am_server_best returns
+    AM_ERR_NONFINITE; a finite request served beside it is unaffected."""
+    clients = _clients(2, cap=32)
+    hs = _handles(am, clients)
+    bad = {k: np.full_like(np.asarray(v, np.float64), np.nan) for k, v in clients[0]["init"].items()}
+    s = am.Server(1 << 28, streams=2, max_per_launch=8, select_best=True, fc_tol=0.05)
+    t0 = s.submit(hs[0], clients[0]["problem"], 0, clients[0]["batch"], 5, bad)
+    t1 = s.submit(hs[1], clients[1]["problem"], 1, clients[1]["batch"], 5, clients[1]["init"])
+    assert s.wait(t0, 60.0)[0] and s.wait(t1, 60.0)[0]
+    with pytest.raises(am.AmError) as e:
+        s.best(t0)
+    assert e.value.code == am.AM_ERR_NONFINITE
+    assert s.best(t1)[0] >= 0
+    s.close()
 
 
 def test_warm_start_reuses_the_multipliers(am):

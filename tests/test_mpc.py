@@ -97,3 +97,47 @@ def test_short_closed_loop_is_finite_and_deterministic():
     for f in ("success", "collided", "reached", "steps", "tracking_error_mean", "accel_mean", "min_clearance",
               "feasible_fraction"):
         assert getattr(r1, f) == getattr(r2, f), f
+
+
+@pytest.mark.gpu
+def test_fp64_closed_loop_matches_an_oracle_driven_loop():
+    """Five control periods of the FP64 closed loop (8 samples, 6 warm-started
+    iterations per period) against the same loop with the FP64 oracle as the
+    solver (its state, and so its multipliers, kept between periods, Sec. IV)
+    and the selection rule written out in numpy: every period selects the
+    same sample, with coefficients within 1e-8."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+
+    def best_rule(res, tol):
+        fin = res[:, 11] == 0
+        ok = fin & (res[:, 0] <= tol)
+        pool = np.flatnonzero(ok) if ok.any() else np.flatnonzero(fin)
+        key = res[pool, 7] if ok.any() else res[pool, 0]
+        return int(pool[np.lexsort((pool, key))[0]])
+
+    class OracleMPC(mpc.MPC):
+        def solve_select(self, pb, init):
+            orc = oracle.Oracle(pb)
+            st = oracle.state_from(pb, init)
+            if self.state is not None:                       # warm start
+                st["lam"][:], st["lampsi"][:] = self.state["lam"], self.state["lampsi"]
+            orc.solve(st, self.K)
+            self.state = st
+            res = orc.residuals(st)
+            idx = best_rule(res, self.fc_tol)
+            return idx, {k: st[k][idx].copy() for k in ("cx", "cc", "cy", "cs", "cpsi")}, res[idx, 0]
+
+    crowd = mpc.crowd_scene("opposite_direction", 5)
+    kw = dict(iters=6, seed=3, dtype="f64")
+    gpu = mpc.MPC(8, **kw)
+    gpu.run(crowd, duration=0.2)
+    ref = OracleMPC(8, **kw)
+    ref.run(crowd, duration=0.2)
+    assert len(gpu.history) == len(ref.history) == 5
+    for (ig, cg), (io, co) in zip(gpu.history, ref.history):
+        assert ig == io
+        for k in cg:
+            np.testing.assert_allclose(cg[k], co[k], atol=1e-8, rtol=0, err_msg=k)
