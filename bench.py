@@ -4,8 +4,9 @@
 One step = one pass of the whole hot path over one batch: the AM solve of
 B = 1000 trajectories for K = 100 iterations (initial projection, then per
 iteration xi1, trajectory evaluation, xi2, xi3/xi4 projections, multiplier
-update) followed by the residual statistics, on synthetic inputs already in
-HBM.  The metric is trajectory-AM-iterations per second (B*K per step).
+update) and the residual statistics of the final state, which the solve
+forms itself, on synthetic inputs already in HBM.  The metric is
+trajectory-AM-iterations per second (B*K per step).
 
 Printed as one JSON line: throughput of the one-launch form, the plain form
 (one launch per sub-step per iteration) beside it, the roofline of the
@@ -107,39 +108,32 @@ def run_gpu(args):
     stream = torch.cuda.current_stream()
 
     def make_states(count):
-        return [am.DeviceState(init, m, n, q, dtype=dtype) for _ in range(count)]
-
-    res_out = torch.empty((B, am.NRES), dtype=torch.float32 if dtype == "f32" else torch.float64, device="cuda")
+        return [am.DeviceState(init, m, n, q, dtype=dtype, residuals=True) for _ in range(count)]
 
     def timed(solver, steps, warmup):
         states = make_states(warmup + steps)
         for s in states[:warmup]:
             solver(s)
-            am.residuals(h, p, s, out=res_out)
         torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-               torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for s, (e0, e1, e2) in zip(states[warmup:], ev):
+        for s, (e0, e1) in zip(states[warmup:], ev):
             e0.record(stream)
             solver(s)
             e1.record(stream)
-            am.residuals(h, p, s, out=res_out)
-            e2.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        solve_ms = [a.elapsed_time(b) for a, b, _ in ev]
-        step_ms = [a.elapsed_time(c) for a, _, c in ev]
+        solve_ms = [a.elapsed_time(b) for a, b in ev]
         last = states[-1]
-        return wall, solve_ms, step_ms, last
+        return wall, solve_ms, solve_ms, last
 
     # launch configuration (tile, register budget): the library's autotuner
     # times each once per shape (setup, not timed)
     (tile, waves), tile_ms = am.autotune(h, p, make_states(1)[0], K)
     fused = lambda s: am.solve(h, p, s, K)
     wall, solve_ms, step_ms, last = timed(fused, args.steps, args.warmup)
-    res = am.residuals(h, p, last).cpu().numpy()
+    res = last.t["res"].cpu().numpy()
     ms_step = wall * 1e3 / args.steps
     value = B * K * args.steps / wall
     avg_kernel_s = float(np.mean(solve_ms)) * 1e-3
@@ -201,12 +195,16 @@ def run_gpu(args):
 
 
 def run_serving(rates, n_requests, modes=("continuous", "plain"), n_clients: int = 32,
-                saturation: int = 64, budget: int = 4 << 30, seed: int = 5):
+                saturation: int = 64, budget: int = 4 << 30, seed: int = 5, max_rate=None, streams: int = 4):
     """Replanning workload c5 through the continuous-batching server: Poisson
     arrivals, per request B ~ U{256..2048}, n ~ U{5..30} moving obstacles,
     5 circles, 20 warm-started AM iterations.  Latency = completion seen by
-    the server's scheduler - submission.  Also a saturation run (all
-    requests submitted at once) for capacity."""
+    the server's scheduler - submission.  Modes: continuous batching (all
+    admissible pending requests of one shape per launch, several launches in
+    flight), sequential (the same fused kernel, one request per launch, one
+    launch at a time) and plain (one request at a time on the per-sub-step
+    path).  max_rate[mode] skips the rates a mode cannot sustain.  Also a
+    saturation run (all requests submitted at once) for capacity."""
     import torch
 
     from paper_2109_13030_amd import am, inputs
@@ -224,8 +222,13 @@ def run_serving(rates, n_requests, modes=("continuous", "plain"), n_clients: int
         # the scheduler polls for 20 ms after its last activity (longer than
         # the mean gap between arrivals at 50-200 Hz), so arrivals do not
         # wait for a thread wake-up
-        srv = am.Server(budget, streams=4, max_per_launch=64, mode=mode_ids[mode], idle_spin_us=20000)
         rng = np.random.default_rng(rseed)
+        # fresh samples per request, drawn before the server starts from a
+        # pool of four sets per robot (drawing them inside the arrival loop
+        # would limit the submission rate)
+        pools = [[inputs.make_initial(inputs.replan_problem(c["problem"], 1), c["batch"],
+                                      int(rng.integers(1 << 31)), cfg.sigma) for _ in range(4)] for c in clients]
+        srv = am.Server(budget, streams=streams, max_per_launch=64, mode=mode_ids[mode], idle_spin_us=20000)
         steps = [0] * len(clients)
         # every robot's first (cold) request is served before the timed run;
         # requests name their shape and the server's KKT cache supplies the
@@ -253,7 +256,7 @@ def run_serving(rates, n_requests, modes=("continuous", "plain"), n_clients: int
             c = clients[i]
             steps[i] += 1
             pb = inputs.replan_problem(c["problem"], steps[i])
-            init = inputs.make_initial(pb, c["batch"], int(rng.integers(1 << 31)), cfg.sigma)
+            init = pools[i][steps[i] % 4]
             tickets.append(srv.submit(None, pb, i, c["batch"], K, init))
             work += c["batch"] * K
         lat = []
@@ -266,15 +269,19 @@ def run_serving(rates, n_requests, modes=("continuous", "plain"), n_clients: int
         wall = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        return {"rate_hz": rate, "requests": count, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        launches = st["launches"] - len(clients)
+        return {"rate_hz": rate, "requests": count, "requests_per_launch": count / max(launches, 1),
+                "p50_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
                 "max_ms": float(lat.max() * 1e3), "traj_iter_per_s": work / wall,
-                "launches": st["launches"] - len(clients), "memory_waits": st["memory_waits"],
+                "launches": launches, "memory_waits": st["memory_waits"],
                 "peak_bytes": st["peak_bytes"]}
 
     for mode in modes:
         rows = []
         for r in rates:
+            if max_rate and mode in max_rate and r > max_rate[mode]:
+                continue
             count = n_requests(r) if callable(n_requests) else n_requests
             rows.append(one(mode, r, count, seed + int(r)))
             print(f"serving {mode} {r:g} Hz: p50 {rows[-1]['p50_ms']:.3f} ms p99 {rows[-1]['p99_ms']:.3f} ms",
@@ -597,12 +604,19 @@ def main():
         return
     if args.serve:
         count = (lambda r: args.serve_requests) if args.serve_requests else (lambda r: int(r * args.serve_seconds))
-        print(json.dumps(run_serving((50.0, 100.0, 200.0), count, saturation=256)),
-              flush=True)
+        rates = (50.0, 100.0, 200.0, 1000.0, 2000.0, 3000.0)
+        sv = run_serving(rates, count, modes=("continuous", "sequential", "plain"), saturation=256,
+                         max_rate={"plain": 200.0})
+        # continuous batching held to one launch in flight: requests that
+        # arrive during a launch share the next one
+        one = run_serving(rates, count, modes=("continuous",), saturation=256, streams=1)
+        sv["modes"]["continuous_one_stream"] = one["modes"]["continuous"]
+        print(json.dumps(sv), flush=True)
         return
     out, pb, init, K = run_gpu(args)
     if not args.no_serve:
-        sv = run_serving((200.0,), 300, saturation=64)
+        sv = run_serving((200.0, 2000.0), lambda r: 300 if r < 1000 else 2000,
+                         modes=("continuous", "sequential", "plain"), saturation=64, max_rate={"plain": 200.0})
         out["serving"] = sv
         cont = sv["modes"]["continuous"][0]
         out["p99_replan_latency_ms"] = cont["p99_ms"]

@@ -147,6 +147,10 @@ typedef struct {
                                       alpha_a, d_a (out; NULL = not written)  */
   void *traj;                      /* device [B][3][q] x, y, psi of the last
                                       iterate (out; NULL = not written)       */
+  void *res;                       /* device [B][AM_NRES] residual statistics
+                                      of the final state, as am_residuals
+                                      writes them, formed by the solve itself
+                                      (out; NULL = not written)               */
 } am_state;
 
 /* Builds the handle: the Bernstein basis, an orthonormal basis of the same

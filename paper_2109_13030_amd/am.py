@@ -58,7 +58,7 @@ class Problem(ct.Structure):
 
 class State(ct.Structure):
     _fields_ = [(k, ct.c_void_p) for k in ("cx", "cc", "cy", "cs", "cpsi", "lam", "lam_psi",
-                                           "alpha", "d", "va", "traj")]
+                                           "alpha", "d", "va", "traj", "res")]
 
 
 class ServerConfig(ct.Structure):
@@ -249,7 +249,7 @@ class DeviceState:
     KEYS = ("cx", "cc", "cy", "cs", "cpsi", "lam", "lam_psi")
 
     def __init__(self, init: dict, m: int, n: int, q: int, dtype: str = "f32", device="cuda",
-                 outputs: bool = True, projections: bool = False):
+                 outputs: bool = True, projections: bool = False, residuals: bool = False):
         torch = _torch()
         dt = _dt(dtype)
         B, nv = np.asarray(init["cx"]).shape
@@ -267,11 +267,12 @@ class DeviceState:
         self.t["va"] = torch.zeros((B, 4, q), dtype=dt, device=device) if projections else None
         self.t["alpha"] = torch.zeros((B, m * n, q), dtype=dt, device=device) if projections else None
         self.t["d"] = torch.zeros((B, m * n, q), dtype=dt, device=device) if projections else None
+        self.t["res"] = torch.zeros((B, NRES), dtype=dt, device=device) if residuals else None
 
     @property
     def c(self) -> State:
         s = State()
-        for k in ("cx", "cc", "cy", "cs", "cpsi", "lam", "lam_psi", "alpha", "d", "va", "traj"):
+        for k in ("cx", "cc", "cy", "cs", "cpsi", "lam", "lam_psi", "alpha", "d", "va", "traj", "res"):
             setattr(s, k, _ptr(self.t.get(k)))
         return s
 

@@ -90,7 +90,7 @@ Desc make_desc(const am_handle *h, const am_problem *p, int32_t batch, int32_t i
   d.ox = p->obs_x; d.oy = p->obs_y; d.oa = p->obs_a; d.ob = p->obs_b;
   d.cx = st->cx; d.cc = st->cc; d.cy = st->cy; d.cs = st->cs; d.cpsi = st->cpsi;
   d.lam = st->lam; d.lampsi = st->lam_psi;
-  d.alpha = st->alpha; d.d = st->d; d.va = st->va; d.traj = st->traj;
+  d.alpha = st->alpha; d.d = st->d; d.va = st->va; d.traj = st->traj; d.res = st->res;
   for (int e = 0; e < 6; ++e) { d.bx[e] = p->bc_x[e]; d.by[e] = p->bc_y[e]; d.bpsi[e] = p->bc_psi[e]; }
   d.offx = 0.5 * (p->bc_x[0] + p->bc_x[3]);
   d.offy = 0.5 * (p->bc_y[0] + p->bc_y[3]);
@@ -548,6 +548,12 @@ int am_solve_batch_plain(am_handle *h, const am_problem *p, int32_t batch, int32
   hipError_t e = amk::launch_plain(d, workspace, workspace_bytes, h->f64, h->shape.nv,
                                    static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "plain path launch");
+  if (st->res) {
+    // the plain path forms the statistics with the residual kernel
+    e = amk::launch_residuals(d, h->c.tP, h->c.tPd, h->c.tPdd, st->res, h->f64, h->shape.nv,
+                              static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "residual kernel launch");
+  }
   return AM_OK;
 }
 

@@ -50,6 +50,8 @@
 //    Pdot 1 = 0).
 #include <hip/hip_runtime.h>
 
+#include <limits>
+
 #include "am_device.h"
 #include "am_internal.h"
 
@@ -606,6 +608,117 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     if (hrow) vaux[2 * A2 + lane] = lampsi0 - rhop * exchange_sum(kXchBig + lane);
     if (prow) vwd[axis * A2 + I] = lam;
     wave_sync();
+  }
+
+  // ---- residual statistics of the final state (am_residuals' columns), on
+  // request: every (circle, obstacle) at this lane's t, the velocity and
+  // acceleration discs, the slack pair, the boundary rows and the cost,
+  // reduced over the lanes and the pair (every wave of the block takes part:
+  // the exchange has a block barrier)
+  if (Dsrc.res) {
+    constexpr int NS = 10;
+    T fc2 = T(0), fcsq = T(0), lvl2 = T(INFINITY), v2 = T(0), a2 = T(0), slk = T(0), head = T(0), bc = T(0),
+      cost = T(0);
+    int bad = 0;
+    if (tv) {
+      for (int j = 0; j < n; ++j) {
+        const Pair<T> o = oxy[j * q + t];
+        const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
+        const T aa = op[j * 8 + OP_A2], bb = op[j * 8 + OP_B2], ab = op[j * 8 + OP_AB];
+        const T dxj = off_x(o.x), dyj = off_y(o.y);
+        for (int i = 0; i < m; ++i) {
+          const T px = dxj + rr[i] * cps, py = dyj + rr[i] * sps;   // circle centre - obstacle
+          const T xt = slack ? dxj + rr[i] * cc : px, yt = slack ? dyj + rr[i] * ss : py;
+          T fx, fy;
+          if (!literal_alpha) {
+            // (a d cos al, b d sin al) = (xt, yt) max(1, ab/r), r = |(b xt, a yt)|;
+            // the zero vector (r^2 below the smallest normal) has al = 0, d = 1
+            const T r2 = bb * xt * xt + aa * yt * yt;
+            const bool zero = !(r2 >= std::numeric_limits<T>::min());
+            const T g = zero ? T(1) : fmax(T(1), ab * Num<T>::rsqrt_fast(r2));
+            fx = zero ? px - a : px - xt * g;
+            fy = zero ? py : py - yt * g;
+          } else {
+            const T al = atan2z(yt, xt);
+            T sa, ca;
+            Num<T>::sincos_(al, &sa, &ca);
+            const T dd = fmax(T(1), (a * xt * ca + b * yt * sa) / (a * a * ca * ca + b * b * sa * sa));
+            fx = px - a * dd * ca;
+            fy = py - b * dd * sa;
+          }
+          const T f2 = fx * fx + fy * fy;
+          fc2 = fmax(fc2, f2);
+          fcsq += f2;
+          lvl2 = fmin(lvl2, px * px / aa + py * py / bb);
+        }
+      }
+      T psd = T(0), psdd = T(0);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        psd += Vb[k] * vzpsi[k];
+        psdd += Wb[k] * vzpsi[k];
+      }
+      v2 = xd * xd + yd * yd;
+      a2 = xdd * xdd + ydd * ydd;
+      slk = fmax(fabs(cc - cps), fabs(ss - sps));
+      const T pi = T(3.14159265358979323846);
+      T dh = atan2z(ss, cc) - psi;
+      dh = dh - T(2) * pi * floor((dh + pi) / (T(2) * pi));
+      head = fabs(dh);
+      cost = xdd * xdd + ydd * ydd + psdd * psdd;
+      if (t == 0 || t == q - 1) {
+        const int o = t == 0 ? 0 : 3;
+        const double vx[3] = {xa, double(xd), double(xdd)}, vy[3] = {ya, double(yd), double(ydd)};
+        const double vp[3] = {double(psi), double(psd), double(psdd)};
+        for (int e = 0; e < 3; ++e) {
+          bc = fmax(bc, T(fabs(vx[e] - Dsrc.bx[o + e])));
+          bc = fmax(bc, T(fabs(vy[e] - Dsrc.by[o + e])));
+          bc = fmax(bc, T(fabs(vp[e] - Dsrc.bpsi[o + e])));
+        }
+      }
+      bad = !isfinite(xa) || !isfinite(ya) || !isfinite(psi);
+    }
+    if (prow) bad |= !isfinite(zl) || !isfinite(lam);
+    if (hrow) bad |= !isfinite(vzpsi[lane]) || !isfinite(vaux[2 * A2 + lane]);
+    auto wmax = [](T v) {
+      for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+      return v;
+    };
+    auto wmin = [](T v) {
+      for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+      return v;
+    };
+    auto wadd = [](T v) {
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      return v;
+    };
+    T stv[NS] = {wmax(T(bad ? 1 : 0)), wmax(fc2), wadd(fcsq), wmin(lvl2), wmax(v2), wmax(a2), wmax(slk),
+                 wmax(head), wmax(bc), wadd(cost)};
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) xmine[k] = stv[k];
+    }
+    __syncthreads();
+    if (live && half == 0 && lane == 0) {
+      const T *ot = xch + kXchHalf;   // the partner's statistics
+      const T fbad = fmax(stv[0], ot[0]), fcmax = Num<T>::sqrt_(fmax(stv[1], ot[1]));
+      const T fcs = stv[2] + ot[2], level = Num<T>::sqrt_(fmin(stv[3], ot[3])) - T(1);
+      const T vex = Num<T>::sqrt_(fmax(stv[4], ot[4])) - vmax, aex = Num<T>::sqrt_(fmax(stv[5], ot[5])) - amax;
+      T *o = static_cast<T *>(Dsrc.res) + size_t(l) * AM_NRES;
+      const int mnq = m * n * q;
+      o[AM_RES_FC_MAX] = fcmax;
+      o[AM_RES_FC_RMS] = mnq ? Num<T>::sqrt_(fcs / T(mnq)) : T(0);
+      o[AM_RES_FV_MAX] = fmax(T(0), vex);
+      o[AM_RES_FA_MAX] = fmax(T(0), aex);
+      o[AM_RES_SLACK_MAX] = fmax(stv[6], ot[6]);
+      o[AM_RES_HEADING_MAX] = fmax(stv[7], ot[7]);
+      o[AM_RES_BC_MAX] = fmax(stv[8], ot[8]);
+      o[AM_RES_COST] = stv[9] + ot[9];
+      o[AM_RES_CLEAR_LEVEL] = mnq ? level : T(INFINITY);
+      o[AM_RES_V_EXCESS] = vex;
+      o[AM_RES_A_EXCESS] = aex;
+      o[AM_RES_NONFINITE] = fbad;
+    }
   }
 
   if (!live) return;   // padding trajectory of a ragged last block

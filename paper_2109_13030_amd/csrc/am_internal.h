@@ -37,7 +37,7 @@ struct Desc {
   const void *ox, *oy, *oa, *ob;
   // state (Bernstein coordinates at the boundary)
   void *cx, *cc, *cy, *cs, *cpsi, *lam, *lampsi;
-  void *alpha, *d, *va, *traj;
+  void *alpha, *d, *va, *traj, *res;
   double bx[6], by[6], bpsi[6];
   double offx, offy;         // translation applied inside the kernel
   double rc, vmax, amax, rho, rho_psi;

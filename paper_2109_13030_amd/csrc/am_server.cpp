@@ -317,7 +317,9 @@ int am_server::launch(Slot &slot) {
       stage += 5 * coef;
       if (hipMemcpyAsync(st.cx, s0, 10 * coef, hipMemcpyHostToDevice, slot.stream) != hipSuccess) return AM_ERR_HIP;
     }
-    hs.push_back(r->h); ps.push_back(p); bs.push_back(r->B); ks.push_back(r->K); sts.push_back(st);
+    am_state sr = st;
+    if (cfg.select_best) sr.res = residuals_of(this, r, r->state);   // formed by the solve itself
+    hs.push_back(r->h); ps.push_back(p); bs.push_back(r->B); ks.push_back(r->K); sts.push_back(sr);
   }
   int rc = AM_OK;
   if (cfg.mode == AM_SERVE_PLAIN) {
@@ -329,12 +331,11 @@ int am_server::launch(Slot &slot) {
   }
   if (rc != AM_OK) return rc;
   if (cfg.select_best) {
-    // residuals of every trajectory, the best one by the selection rule, and
-    // its record to pinned memory (read at retirement)
+    // the best trajectory by the selection rule from the residual rows the
+    // solve wrote, and its record to pinned memory (read at retirement)
     for (size_t i = 0; i < slot.reqs.size(); ++i) {
       Request *r = slot.reqs[i];
       char *res = residuals_of(this, r, r->state), *rec = best_of(this, r, r->state);
-      if ((rc = am_residuals(r->h, &ps[i], r->B, &sts[i], res, slot.stream)) != AM_OK) return rc;
       if ((rc = am_select_best(r->h, r->B, res, cfg.fc_tol, reinterpret_cast<int32_t *>(rec + 2 * es), rec,
                                slot.stream)) != AM_OK)
         return rc;

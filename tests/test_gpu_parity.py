@@ -268,6 +268,57 @@ def test_f32_residuals_full_c2_match_f64_residuals_of_the_same_state():
         np.testing.assert_allclose(r32[:, j], r64[:, j], atol=2e-4, rtol=1e-4, err_msg=name)
 
 
+@pytest.mark.parametrize("flags", [0, 1, 2])
+@pytest.mark.parametrize("plain", [False, True])
+def test_solve_residuals_match_oracle_f64(flags, plain):
+    """The residual statistics a solve writes itself (am_state.res: the fused
+    kernel's epilogue, the plain path's residual kernel) against the oracle's
+    residuals of its own final state (FP64, c1 at 30 iterations, ragged
+    batch), under the default angle, the literal angle and the slack copies."""
+    import torch
+    from paper_2109_13030_amd import am
+    pb, init = inputs.workload("c1", batch=7)
+    pb = dict(pb, flags=flags)
+    h = am.Handle.for_problem(pb, "f64")
+    p = am.DeviceProblem(pb, "f64")
+    st = am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f64", residuals=True)
+    if plain:
+        ws = torch.empty(am.plain_workspace_size(h, st.B), dtype=torch.uint8, device="cuda")
+        am.solve_plain(h, p, st, 30, ws)
+    else:
+        am.solve(h, p, st, 30)
+    torch.cuda.synchronize()
+    got = st.t["res"].cpu().numpy()
+    orc, ost = H.run_oracle(pb, init, 30)
+    ref = orc.residuals(ost)
+    np.testing.assert_allclose(got, ref, atol=1e-7, rtol=1e-6)
+
+
+def test_solve_residuals_full_c2_f32():
+    """At the benchmark's size (FP32, B = 1000, K = 100) the statistics of the
+    fused kernel's epilogue equal the FP64 residual kernel's on the same
+    final coefficients, to the bound of the test above (the epilogue
+    evaluates the positions in FP64 from the orthonormal coefficients, the
+    residual kernel from the Bernstein ones)."""
+    import torch
+    from paper_2109_13030_amd import am
+    pb, init = inputs.workload("c2")
+    h = am.Handle.for_problem(pb, "f32")
+    p = am.DeviceProblem(pb, "f32")
+    st = am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32", residuals=True)
+    am.solve(h, p, st, 100)
+    torch.cuda.synchronize()
+    got = st.t["res"].cpu().numpy()
+    out = st.numpy()
+    same = {k: out[k] for k in am.DeviceState.KEYS}
+    h64 = am.Handle.for_problem(pb, "f64")
+    p64 = am.DeviceProblem(pb, "f64")
+    st64 = am.DeviceState(same, len(pb["r"]), len(pb["oa"]), pb["q"], dtype="f64")
+    r64 = am.residuals(h64, p64, st64).cpu().numpy()
+    for j, name in enumerate(am.RES_NAMES):
+        np.testing.assert_allclose(got[:, j], r64[:, j], atol=2e-4, rtol=1e-4, err_msg=name)
+
+
 def _odd_horizon_problem(q, B=5):
     import dataclasses
     cfg = dataclasses.replace(inputs.CONFIGS["c2"], q=q)

@@ -280,8 +280,9 @@ def test_select_best_rule_on_planted_rows(am, dtype):
 
 def test_server_reports_the_best_trajectory(am):
     """With select_best the server returns, per request, the trajectory that
-    the selection rule picks from the residuals of its own result: the same
-    index as residuals + am_select_best on the direct batch solve."""
+    the selection rule picks from the residuals its solve wrote: the same
+    index, cost and residual as the rule applied to the residuals of the
+    direct batch solve."""
     import torch
     clients = _clients(4)
     hs = _handles(am, clients)
@@ -294,11 +295,10 @@ def test_server_reports_the_best_trajectory(am):
     s.close()
     for (h, c), (idx, cost, fc) in zip(zip(hs, clients), got):
         p = am.DeviceProblem(c["problem"], "f32")
-        ds = am.DeviceState(c["init"], 5, c["n"], c["problem"]["q"], "f32")
+        ds = am.DeviceState(c["init"], 5, c["n"], c["problem"]["q"], "f32", residuals=True)
         am.solve(h, p, ds, K)
-        res = am.residuals(h, p, ds)
         torch.cuda.synchronize()
-        r = res.cpu().numpy()
+        r = ds.t["res"].cpu().numpy()
         want = _best_rule(r, np.float32(0.05))
         assert idx == want
         assert cost == pytest.approx(float(r[want, 7]), rel=0, abs=0)
