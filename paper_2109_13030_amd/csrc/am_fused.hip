@@ -34,9 +34,10 @@
 //    N = M1 Q.  Every term on the right but z is small once the iteration
 //    settles, so the FP32 rounding of the operators and of the large product
 //    F^T F z no longer enters z; z, the multipliers and the update itself are
-//    carried in FP64, and so are the positions x = U z and their offsets
-//    from the obstacle centres.  A z = b holds after the first update, so
-//    the boundary term is applied once.
+//    carried in FP64, and so are the positions (x' = x + U dz, the product
+//    of the small update in T) and their offsets from the obstacle centres.
+//    A z = b holds after the first update, so the boundary term is applied
+//    once.
 //  * The heading step (eq. compute_convex_surrogate) needs M2 (lambda_psi +
 //    rho U^T psi_hat).  The kernel carries mu = M2 lambda_psi instead of
 //    lambda_psi and reduces with the rows of U~ = U M2^T, so one reduction
@@ -226,10 +227,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
           *gW = static_cast<const T *>(Dsrc.W), *gUt = static_cast<const T *>(Dsrc.Ut),
           *gM2 = static_cast<const T *>(Dsrc.M2);
   T Ub[NV], Vb[NV], Wb[NV], Ut[NV];
-  double Ubd[NV];   // FP64 rows for the positions
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    Ubd[k] = tv ? Dsrc.Ud[tt * NV + k] : 0.0;
     Ub[k] = tv ? gU[tt * NV + k] : T(0);
     Vb[k] = tv ? gV[tt * NV + k] : T(0);
     Wb[k] = tv ? gW[tt * NV + k] : T(0);
@@ -296,23 +295,43 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   wave_sync();
 
   // ---- per-lane trajectory values at t: positions (absolute, FP64) and
-  // the other channels (T)
-  double xa, ya;
+  // the other channels (T).  The positions are formed from the FP64
+  // coefficients once and then carried: x' = x + U dz, the product of the
+  // small update in T added in FP64 (as N z above).
+  double xa = 0.0, ya = 0.0;
+  if (tv) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double u = Dsrc.Ud[tt * NV + k];
+      xa += u * vzd[k];
+      ya += u * vzd[A2 + k];
+    }
+  }
+  xa += offx;
+  ya += offy;
   T xd, xdd, cc, yd, ydd, ss, psi, cps, sps, psih;
   T racc = T(0);   // sum over the iterations of psi_sign (psi - psi_hat) at t
 
-  auto eval_xy = [&]() {
-    double a0 = 0.0, b0 = 0.0;
-    T a1 = 0, a2 = 0, a3 = 0, b1 = 0, b2 = 0, b3 = 0;
+  // derivatives and slack channels from z; positions advanced by dz when
+  // `step` is set
+  auto eval_xy = [&](bool step) {
+    T a0 = 0, b0 = 0, a1 = 0, a2 = 0, a3 = 0, b1 = 0, b2 = 0, b3 = 0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       const T zx = vz[k], zc = vz[NV + k], zy = vz[A2 + k], zs = vz[A2 + NV + k];
-      a0 += Ubd[k] * vzd[k]; b0 += Ubd[k] * vzd[A2 + k];
+      if (step) {
+        a0 += Ub[k] * vdz[k];
+        b0 += Ub[k] * vdz[A2 + k];
+      }
       a1 += Vb[k] * zx; a2 += Wb[k] * zx; a3 += Ub[k] * zc;
       b1 += Vb[k] * zy; b2 += Wb[k] * zy; b3 += Ub[k] * zs;
     }
-    xa = a0 + offx; xd = a1; xdd = a2; cc = a3;
-    ya = b0 + offy; yd = b1; ydd = b2; ss = b3;
+    if (step) {
+      xa += double(a0);
+      ya += double(b0);
+    }
+    xd = a1; xdd = a2; cc = a3;
+    yd = b1; ydd = b2; ss = b3;
   };
   // offset of this lane's robot centre from an obstacle centre, formed in
   // FP64 and rounded once
@@ -534,7 +553,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   };
 
   // ---- step 1 of the AM list: initial xi3, xi4 from the given trajectory
-  eval_xy();
+  eval_xy(false);
   eval_psi();
   psih = psi;
   // rows I of M1 and N (position block), read from LDS in every product
@@ -557,12 +576,11 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     bcc = 0.0;
     zl += dz;
     if (prow) {
-      vzd[axis * A2 + I] = zl;
       vz[axis * A2 + I] = T(zl);
       vdz[axis * A2 + I] = T(dz);
     }
     wave_sync();
-    eval_xy();
+    eval_xy(true);
     // N z of the new z, used by the next update
     nz += double(n_dot(vdz + axis * A2));
 
@@ -606,7 +624,10 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     if (lane < NV) xmine[kXchBig + lane] = s;
     __syncthreads();
     if (hrow) vaux[2 * A2 + lane] = lampsi0 - rhop * exchange_sum(kXchBig + lane);
-    if (prow) vwd[axis * A2 + I] = lam;
+    if (prow) {
+      vzd[axis * A2 + I] = zl;
+      vwd[axis * A2 + I] = lam;
+    }
     wave_sync();
   }
 
