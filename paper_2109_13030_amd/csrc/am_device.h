@@ -89,9 +89,11 @@ struct Num<double> {
 
 // atan2 with the value 0 for the zero vector (the angle of a zero vector is
 // not defined by the paper; this reading is used everywhere).
+// (evaluated on every lane and then selected, without a branch)
 template <typename T>
 __device__ __forceinline__ T atan2z(T y, T x) {
-  return (x == T(0) && y == T(0)) ? T(0) : Num<T>::atan2_(y, x);
+  const T a = Num<T>::atan2_(y, x);
+  return (x == T(0) && y == T(0)) ? T(0) : a;
 }
 
 // Orders LDS traffic between lanes of one wavefront (the compiler may not

@@ -268,14 +268,14 @@ __device__ __forceinline__ void stv(T *p, const Vec<T, V> &x) {
 // rows per chunk of loads (fewer for FP64 and for two steps per item)
 template <typename T, int V> constexpr int kProjChunk = (sizeof(T) == 4 ? 8 : 4) / V;
 
-template <typename T, int V>
+template <typename T, int V, bool LITERAL>
 __global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
   __shared__ T ell[4][AM_MAX_OBS];  // a_j, b_j (grown by the circle radius), 1/a_j^2, 1/b_j^2
   const int q = D.q, m = D.m, n = D.n;
   const int qv = q / V;   // items per row; V divides q
   const int per = (m + 1) * qv;
   const int g = int(blockIdx.x) * kThreads + int(threadIdx.x);
-  const bool slack = D.flags & AM_XTILDE_SLACK, literal = D.flags & AM_ALPHA_LITERAL;
+  const bool slack = D.flags & AM_XTILDE_SLACK;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     const T a = static_cast<const T *>(D.oa)[j] + T(D.rc), b = static_cast<const T *>(D.ob)[j] + T(D.rc);
     ell[0][j] = a;
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
           // offset of the robot centre from the obstacle centre in FP64,
           // rounded once
           const T xt = T(xv.v[e] - double(gx[u].v[e])) + rx[e], yt = T(yv.v[e] - double(gy[u].v[e])) + ry[e];
-          if (!literal) {
+          if constexpr (!LITERAL) {
             // elliptic angle: the point (a d cos al, b d sin al) is (xt, yt)
             // itself, so d = sqrt(xt^2/a^2 + yt^2/b^2) (eq. compute_zeta_3)
             al.v[e] = atan2z(a * yt, b * xt);
@@ -346,16 +346,17 @@ __global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
     const Vec<T, V> xdv = ldv<T, V>(tr + q + t), ydv = ldv<T, V>(tr + 5 * q + t);
     const Vec<T, V> xddv = ldv<T, V>(tr + 2 * q + t), yddv = ldv<T, V>(tr + 6 * q + t);
     Vec<T, V> av, dv, aa, da;
+    const T ivmax = T(1) / T(D.vmax), iamax = T(1) / T(D.amax);
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       const T xd = xdv.v[e], yd = ydv.v[e], xdd = xddv.v[e], ydd = yddv.v[e];
+      // with alpha_v = atan2(ydot, xdot), xdot cos alpha_v + ydot sin alpha_v
+      // is the speed itself, so d_v = min(1, |v| / v_max) (eq. compute_dv
+      // clipped to [0, 1]); likewise d_a
       av.v[e] = atan2z(yd, xd);
       aa.v[e] = atan2z(ydd, xdd);
-      T sv, cv, sa, ca;
-      Num<T>::sincos_(av.v[e], &sv, &cv);
-      Num<T>::sincos_(aa.v[e], &sa, &ca);
-      dv.v[e] = fmin(T(1), fmax(T(0), (xd * cv + yd * sv) / T(D.vmax)));
-      da.v[e] = fmin(T(1), fmax(T(0), (xdd * ca + ydd * sa) / T(D.amax)));
+      dv.v[e] = fmin(T(1), Num<T>::sqrt_(xd * xd + yd * yd) * ivmax);
+      da.v[e] = fmin(T(1), Num<T>::sqrt_(xdd * xdd + ydd * ydd) * iamax);
     }
     stv<T, V>(o + t, av);
     stv<T, V>(o + q + t, dv);
@@ -368,10 +369,13 @@ __global__ __launch_bounds__(kThreads) void k_project(Desc D, Ptrs<T> w) {
 template <typename T>
 void project(const Desc &D, const Ptrs<T> &w, hipStream_t st) {
   const size_t rows = size_t(D.B) * (D.m + 1);
+  const bool lit = D.flags & AM_ALPHA_LITERAL;
   if (D.q % 2 == 0)
-    hipLaunchKernelGGL((k_project<T, 2>), dim3(blocks_for(rows * (D.q / 2))), dim3(kThreads), 0, st, D, w);
+    hipLaunchKernelGGL((lit ? k_project<T, 2, true> : k_project<T, 2, false>), dim3(blocks_for(rows * (D.q / 2))),
+                       dim3(kThreads), 0, st, D, w);
   else
-    hipLaunchKernelGGL((k_project<T, 1>), dim3(blocks_for(rows * D.q)), dim3(kThreads), 0, st, D, w);
+    hipLaunchKernelGGL((lit ? k_project<T, 1, true> : k_project<T, 1, false>), dim3(blocks_for(rows * D.q)),
+                       dim3(kThreads), 0, st, D, w);
 }
 
 // ---- residual channels of F xi - g per (l, t), reading alpha and d.  Item
