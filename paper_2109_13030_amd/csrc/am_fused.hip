@@ -38,14 +38,16 @@
 //    of the small update in T) and their offsets from the obstacle centres.
 //    A z = b holds after the first update, so the boundary term is applied
 //    once.
-//  * The heading step (eq. compute_convex_surrogate) needs M2 (lambda_psi +
-//    rho U^T psi_hat).  The kernel carries mu = M2 lambda_psi instead of
-//    lambda_psi and reduces with the rows of U~ = U M2^T, so one reduction
-//    gives M2 U^T psi_hat directly; the multiplier update (eq.
-//    update_lambda_psi) becomes mu <- mu - rho_psi U~^T (psi - psi_hat).
-//    lambda_psi itself is linear in the summed residuals, so each lane sums
-//    psi - psi_hat over the iterations and lambda_psi is formed once at the
-//    end.
+//  * The heading step (eq. compute_convex_surrogate) is z_psi = h_psi +
+//    M2 (lambda_psi + rho U^T psi_hat).  With mu = M2 lambda_psi and the rows
+//    of U~ = U M2^T, z_psi = h_psi + mu + rho U~^T psi_hat, and the
+//    multiplier update (eq. update_lambda_psi) is mu <- mu - rho_psi U~^T
+//    (psi - psi_hat).  Both sums fold into one per iteration: z_psi of
+//    iteration k+1 is that of iteration k plus U~^T (rho (psi_hat' -
+//    psi_hat) - rho_psi (psi - psi_hat)), so the kernel carries z_psi (FP64)
+//    and reduces that per-lane difference only.  lambda_psi itself is
+//    linear in the summed residuals, so each lane sums psi - psi_hat over
+//    the iterations and lambda_psi is formed once at the end.
 //  * Coefficients are shifted by the midpoint of start and goal on entry and
 //    back on exit (exact: the basis reproduces constants, P 1 = 1,
 //    Pdot 1 = 0).
@@ -175,7 +177,7 @@ template <typename T, int NV, int C, int RED>
 __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds, const FusedLds &L,
                            int lane, int wave) {
   constexpr int A2 = pad4(2 * NV), N2 = 2 * NV;
-  constexpr int G = 5 * NV;   // rows of the per-iteration reduction
+  constexpr int G = 4 * NV;   // rows of the per-iteration reduction
   constexpr int DW = int(sizeof(double) / sizeof(T));   // elements of T per FP64 value
   // descriptor fields used in the loop, as locals
   const int q = uni(Dsrc.q), m = uni(Dsrc.m), n = uni(Dsrc.n), flags = uni(Dsrc.flags), K = uni(Dsrc.K);
@@ -372,10 +374,10 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 
   // ---- xi3/xi4 projection of every (circle, obstacle, t), velocity and
   // acceleration, then the per-wave partial sums of F^T (F xi - g) (rows
-  // 0..4nv-1) and U~^T (psi - psi_hat) (rows 4nv..5nv-1), exchanged between
-  // the two waves; afterwards lane k < 4nv holds row k of the total in `tr`
-  // and lane k < nv row 4nv+k in `trpsi`.
-  T tr = T(0), trpsi = T(0);
+  // 0..4nv-1), exchanged between the two waves; afterwards lane k < 4nv
+  // holds row k of the total in `tr`.  `rp` keeps this lane's heading
+  // residual psi_sign (psi - psi_hat) for the next heading step.
+  T tr = T(0), rp = T(0);
   // near-obstacle set of the last vote and the positions it was taken at
   T xvote = T(0), yvote = T(0), extvote = T(0);
   uint64_t near_set = 0;
@@ -514,11 +516,10 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const T k1 = slack ? T(0) : s1, k2 = (slack ? T(0) : s2) + T(1);
     const T ro1x = k1 * dc - Dx, ro2x = k2 * dc - DRx;
     const T ro1y = k1 * ds - Dy, ro2y = k2 * ds - DRy;
-    const T rp = with_psi ? psi_sign * (psi - psih) : T(0);
+    rp = with_psi ? psi_sign * (psi - psih) : T(0);
     racc += rp;
     // partials of F^T (F xi - g) (x: rows 0..2nv-1, y: 2nv..4nv-1, as
-    // [V W U] on the position block and U on the slack block) and of
-    // U~^T (psi - psi_hat) (rows 4nv..5nv-1)
+    // [V W U] on the position block and U on the slack block)
     // (the velocity and acceleration rows are usually inside their discs on
     // every lane of the wave; their terms are then zero and are left out)
     T pr[G];
@@ -539,7 +540,6 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     for (int k = 0; k < NV; ++k) {
       pr[NV + k] = Ub[k] * ro2x;
       pr[3 * NV + k] = Ub[k] * ro2y;
-      pr[4 * NV + k] = Ut[k] * rp;
     }
     // the reduction and exchange are the pair's critical path: while a wave
     // is in them the SIMD issues its instructions first
@@ -548,7 +548,6 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     if (lane < G) xmine[lane] = tot;
     __syncthreads();
     if (prow) tr = exchange_sum(lane);
-    if (hrow) trpsi = exchange_sum(4 * NV + lane);
     __builtin_amdgcn_s_setprio(0);
   };
 
@@ -566,6 +565,9 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   project_reduce(false);
   if (prow) vw[axis * A2 + I] = T(lam - rhod * double(tr));
   wave_sync();
+  // heading coefficients before the first step's sum: h_psi + M2 lambda_psi
+  double zpsi_d = double(hpsi) + double(mu);
+  T psih_prev = T(0);
 
   for (int it = 0; it < K; ++it) {
     // ---- xi1 (eqs. over_3, zeta_1_sepration_3) as an update of z:
@@ -585,22 +587,30 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     nz += double(n_dot(vdz + axis * A2));
 
     // ---- xi2: psi_hat = atan2(s, c) on the branch nearest psi^k, then the
-    // heading QP (eq. compute_convex_surrogate):
-    // z_psi = h + M2 lambda_psi + rho M2 U^T psi_hat = h + mu + rho U~^T psi_hat
+    // heading QP (eq. compute_convex_surrogate) with the multiplier update
+    // of the previous iteration folded in:
+    // z_psi += U~^T (rho (psi_hat' - psi_hat) - rho_psi psi_sign (psi - psi_hat))
+    T dpsi;
     {
       T ph;
       if (unwrap) ph = psi + atan2z(ss * cps - cc * sps, cc * cps + ss * sps);
       else ph = atan2z(ss, cc);
-      psih = tv ? ph : T(0);
+      const T pnew = tv ? ph : T(0);
+      dpsi = rho * (pnew - psih_prev) - rhop * rp;
+      psih_prev = pnew;
+      psih = pnew;
     }
     T pp[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) pp[k] = Ut[k] * psih;
+    for (int k = 0; k < NV; ++k) pp[k] = Ut[k] * dpsi;
     __builtin_amdgcn_s_setprio(2);
     const T upsi = wave_sum_many<T, NV, RED>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = upsi;
     __syncthreads();
-    if (hrow) vzpsi[lane] = hpsi + mu + rho * exchange_sum(kXchBig + lane);
+    if (hrow) {
+      zpsi_d += double(exchange_sum(kXchBig + lane));
+      vzpsi[lane] = T(zpsi_d);
+    }
     __builtin_amdgcn_s_setprio(0);
     wave_sync();
     eval_psi();
@@ -611,7 +621,6 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       lam -= rhod * double(tr);
       vw[axis * A2 + I] = T(lam - rhod * double(tr));
     }
-    if (hrow) mu -= rhop * trpsi;
     wave_sync();
   }
 
