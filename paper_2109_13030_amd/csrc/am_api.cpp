@@ -87,6 +87,7 @@ Desc make_desc(const am_handle *h, const am_problem *p, int32_t batch, int32_t i
   const Consts &c = h->c;
   d.U = c.tU; d.V = c.tV; d.W = c.tW; d.M1 = c.tM1; d.H1 = c.tH1; d.M2 = c.tM2; d.H2 = c.tH2;
   d.GF = c.tGF; d.N = c.tN; d.Ut = c.tUt; d.R = c.R; d.Rinv = c.Rinv; d.Ud = c.U; d.Abc = c.Abc; d.H1d = c.H1;
+  d.Qd = c.G + 2 * size_t(h->shape.nv) * h->shape.nv;   // the third Gram matrix, W^T W
   d.ox = p->obs_x; d.oy = p->obs_y; d.oa = p->obs_a; d.ob = p->obs_b;
   d.cx = st->cx; d.cc = st->cc; d.cy = st->cy; d.cs = st->cs; d.cpsi = st->cpsi;
   d.lam = st->lam; d.lampsi = st->lam_psi;

@@ -30,14 +30,14 @@
 //  * The xi1 step is applied as an update of the current coefficients.  With
 //    [M1 H1] the first block row of the KKT inverse (eq. over_3), the identity
 //    M1 (Q + rho F^T F) + H1 A = I turns z' = H1 b + M1 (lambda + rho F^T g)
-//    into z' = z - H1 (A z - b) + M1 (lambda - rho F^T (F xi - g)) - N z with
-//    N = M1 Q.  Every term on the right but z is small once the iteration
-//    settles, so the FP32 rounding of the operators and of the large product
-//    F^T F z no longer enters z; z, the multipliers and the update itself are
-//    carried in FP64, and so are the positions (x' = x + U dz, the product
-//    of the small update in T) and their offsets from the obstacle centres.
-//    A z = b holds after the first update, so the boundary term is applied
-//    once.
+//    into z' = z - H1 (A z - b) + M1 (lambda - rho F^T (F xi - g) - Q z).
+//    The update is small once the iteration settles, so the FP32 rounding of
+//    the operators and of the large product F^T F z no longer enters z; z,
+//    the multipliers, Q z and the update itself are carried in FP64 (Q z' =
+//    Q z + Q dz with the product of the small update in T; Q is the
+//    block-diagonal smoothness term W^T W), and so are the positions (x' =
+//    x + U dz likewise) and their offsets from the obstacle centres.  A z = b
+//    holds after the first update, so the boundary term is applied once.
 //  * The heading step (eq. compute_convex_surrogate) is z_psi = h_psi +
 //    M2 (lambda_psi + rho U^T psi_hat).  With mu = M2 lambda_psi and the rows
 //    of U~ = U M2^T, z_psi = h_psi + mu + rho U~^T psi_hat, and the
@@ -154,25 +154,6 @@ __device__ __forceinline__ T row_dot(const T *op, int I, const T *v) {
   return acc0 + acc1;
 }
 
-// The same with an FP64 vector, accumulated in FP64.
-template <typename T, int NV>
-__device__ __forceinline__ double row_dot_d(const T *op, int I, const double *v) {
-  constexpr int N2 = 2 * NV, C = pad4(N2) / 4;
-  const Quad<T> *o = reinterpret_cast<const Quad<T> *>(op);
-  const Pair<double> *vv = reinterpret_cast<const Pair<double> *>(v);
-  double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const Quad<T> a = o[c * N2 + I];
-    const Pair<double> b0 = vv[2 * c], b1 = vv[2 * c + 1];
-    acc0 += double(a.a) * b0.x;
-    acc1 += double(a.b) * b0.y;
-    if (4 * c + 2 < N2) acc0 += double(a.c) * b1.x;
-    if (4 * c + 3 < N2) acc1 += double(a.d) * b1.y;
-  }
-  return acc0 + acc1;
-}
-
 template <typename T, int NV, int C, int RED>
 __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds, const FusedLds &L,
                            int lane, int wave) {
@@ -201,7 +182,9 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   const Pair<T> *oxy = reinterpret_cast<const Pair<T> *>(lds + L.oxy);
   const T *op = lds + L.op;
   const Quad<T> *opq = reinterpret_cast<const Quad<T> *>(lds + L.op);
-  const T *M1 = lds + L.m1, *NQ = lds + L.gf;
+  constexpr int QS = pad4(NV);   // row stride of the Q rows and block stride of dz
+  static_assert(QS + NV <= A2, "both blocks of dz fit one axis's area");
+  const T *M1 = lds + L.m1, *QL = lds + L.gf;
   const WaveLds wl = wave_layout(NV, RED, DW);
   T *wb = lds + L.wave0 + wave * L.wave_stride;
   T *vz = wb + wl.z, *vzpsi = wb + wl.zpsi, *vaux = wb + wl.aux;
@@ -555,15 +538,33 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   eval_xy(false);
   eval_psi();
   psih = psi;
-  // rows I of M1 and N (position block), read from LDS in every product
-  // (in registers they would push the kernel past its register budget)
+  // row I of M1 (position block), read from LDS in every product (in
+  // registers it would push the kernel past its register budget)
   auto m1_dot = [&](const T *v) { return row_dot<T, NV>(M1, I, v); };
-  auto n_dot = [&](const T *v) { return row_dot<T, NV>(NQ, I, v); };
-  // N z, formed once in FP64 and then carried: N z' = N z + N dz, the
-  // product of the small update in T
-  double nz = row_dot_d<T, NV>(NQ, I, vzd + axis * A2);
+  // row I of Q = blockdiag(W^T W, W^T W or 0) times the block of dz it
+  // meets (dz is stored with its blocks QS apart; the padding reads zero)
+  const int qb = I / NV, qi = I - qb * NV;
+  auto q_dot = [&]() {
+    const Quad<T> *o = reinterpret_cast<const Quad<T> *>(QL + (qb * NV + qi) * QS);
+    const Quad<T> *v = reinterpret_cast<const Quad<T> *>(vdz + axis * A2 + qb * QS);
+    T acc0 = T(0), acc1 = T(0);
+#pragma unroll
+    for (int c = 0; c < QS / 4; ++c) {
+      const Quad<T> a = o[c], b = v[c];
+      acc0 += a.a * b.a;
+      acc1 += a.b * b.b;
+      acc0 += a.c * b.c;
+      acc1 += a.d * b.d;
+    }
+    return acc0 + acc1;
+  };
+  // Q z, formed once in FP64 and then carried: Q z' = Q z + Q dz
+  double qz = 0.0;
+  if (prow && (qb == 0 || !(flags & AM_Q_CS_ZERO))) {
+    for (int k = 0; k < NV; ++k) qz += Dsrc.Qd[qi * NV + k] * vzd[axis * A2 + qb * NV + k];
+  }
   project_reduce(false);
-  if (prow) vw[axis * A2 + I] = T(lam - rhod * double(tr));
+  if (prow) vw[axis * A2 + I] = T((lam - rhod * double(tr)) - qz);
   wave_sync();
   // heading coefficients before the first step's sum: h_psi + M2 lambda_psi
   double zpsi_d = double(hpsi) + double(mu);
@@ -571,20 +572,18 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 
   for (int it = 0; it < K; ++it) {
     // ---- xi1 (eqs. over_3, zeta_1_sepration_3) as an update of z:
-    // z' = z - H1 (A z - b) + M1 (lambda - rho F^T (F xi - g)) - N z
+    // z' = z - H1 (A z - b) + M1 (lambda - rho F^T (F xi - g) - Q z)
     // (every lane computes; lanes past the position rows compute a copy of
     // row 0 and store nothing)
-    const double dz = (double(m1_dot(vw + axis * A2)) - nz) - bcc;
+    const double dz = double(m1_dot(vw + axis * A2)) - bcc;
     bcc = 0.0;
     zl += dz;
     if (prow) {
       vz[axis * A2 + I] = T(zl);
-      vdz[axis * A2 + I] = T(dz);
+      vdz[axis * A2 + qb * QS + qi] = T(dz);
     }
     wave_sync();
     eval_xy(true);
-    // N z of the new z, used by the next update
-    nz += double(n_dot(vdz + axis * A2));
 
     // ---- xi2: psi_hat = atan2(s, c) on the branch nearest psi^k, then the
     // heading QP (eq. compute_convex_surrogate) with the multiplier update
@@ -615,11 +614,14 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     wave_sync();
     eval_psi();
 
+    // Q z of the new z, for the next update's right-hand side
+    qz += double(q_dot());
+
     // ---- xi3, xi4 and the multipliers (eqs. update_lambda_1, update_lambda_psi)
     project_reduce(true);
     if (prow) {
       lam -= rhod * double(tr);
-      vw[axis * A2 + I] = T(lam - rhod * double(tr));
+      vw[axis * A2 + I] = T((lam - rhod * double(tr)) - qz);
     }
     wave_sync();
   }
@@ -839,12 +841,20 @@ __device__ __forceinline__ void fused_block(const Desc &D) {
     o[OP_A2] = a * a; o[OP_B2] = b * b; o[OP_AB] = a * b; o[OP_AMAX] = fmax(a, b);
     o[OP_A] = a; o[OP_B] = b; o[6] = T(0); o[7] = T(0);
   }
-  const T *gM1 = static_cast<const T *>(D.M1), *gN = static_cast<const T *>(D.N);
+  const T *gM1 = static_cast<const T *>(D.M1);
   for (int e = tid; e < A2 * N2; e += blockDim.x) {
     // element e of the Quad layout: chunk c, row I, component e % 4
     const int c = e / (4 * N2), rem = e % (4 * N2), I = rem / 4, J = 4 * c + rem % 4;
     lds[L.m1 + e] = J < N2 ? gM1[I * N2 + J] : T(0);
-    lds[L.gf + e] = J < N2 ? gN[I * N2 + J] : T(0);
+  }
+  // Q rows: [block][row][pad4(nv)], the slack block zero under AM_Q_CS_ZERO
+  {
+    constexpr int QS = pad4(NV);
+    const bool qcs = !(uni(D.flags) & AM_Q_CS_ZERO);
+    for (int e = tid; e < 2 * NV * QS; e += blockDim.x) {
+      const int bq = e / (NV * QS), rem = e % (NV * QS), i = rem / QS, k = rem % QS;
+      lds[L.gf + e] = (k < NV && (bq == 0 || qcs)) ? T(D.Qd[i * NV + k]) : T(0);
+    }
   }
   for (int i = tid; i < 2 * TILE * L.wave_stride; i += blockDim.x) lds[L.wave0 + i] = T(0);
   __syncthreads();

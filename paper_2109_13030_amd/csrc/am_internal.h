@@ -33,6 +33,7 @@ struct Desc {
   const double *Ud;          // [q][nv] U in FP64 (positions)
   const double *Abc;         // [6][nv] boundary rows U, V, W at t = 0 and t = q-1 (z basis)
   const double *H1d;         // [2nv][6] H1 in FP64
+  const double *Qd;          // [nv][nv] W^T W in the z basis (FP64): the smoothness block of Q
   // problem
   const void *ox, *oy, *oa, *ob;
   // state (Bernstein coordinates at the boundary)
