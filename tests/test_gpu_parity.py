@@ -119,6 +119,42 @@ def test_no_obstacles_and_single_circle_f64():
     _compare_f64(pb1, init, 20)
 
 
+def _nv8(name, B):
+    """A workload with 8 Bernstein coefficients per variable (the library's
+    other basis size): the problem of `name` with nv = 8 and fresh samples."""
+    pb, _ = inputs.workload(name, batch=1)
+    pb = dict(pb, nv=8)
+    return pb, inputs.make_initial(pb, B, inputs.config_seed(name) + 8, 0.5)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_nv8_f64_matches_oracle(plain):
+    """The nv = 8 kernel instances (fused and plain) follow the oracle at FP64."""
+    pb, init = _nv8("c1", 7)
+    _compare_f64(pb, init, 12, plain=plain)
+
+
+def test_nv8_f32_within_tolerance():
+    """The nv = 8 FP32 instances (every launch configuration) against the
+    oracle at 1e-3 m / 1e-3 rad, 300 trajectories of a c2-like problem."""
+    from paper_2109_13030_amd import am
+    pb, init = _nv8("c2", 300)
+    h = am.Handle.for_problem(pb, "f32")
+    p = am.DeviceProblem(pb, "f32")
+    ref = None
+    for tile, waves in am.LAUNCHES:
+        h.tile, h.waves = tile, waves
+        st = am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32")
+        am.solve(h, p, st, 60)
+        out = st.numpy()
+        if ref is None:
+            ref = out
+            _fp32_gate(pb, init, 60, out=out)
+        else:
+            for k in ("cx", "cy", "cpsi", "lam", "lam_psi"):
+                assert np.array_equal(out[k], ref[k]), (tile, waves, k)
+
+
 def test_warm_start_continues_the_iteration_f64():
     """K1 iterations then K2 more from the returned state = K1 + K2 at once."""
     from paper_2109_13030_amd import am
