@@ -232,30 +232,50 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const int b = axis * 2 + (I >= NV), kk = I % NV;
     const T *src = static_cast<const T *>(b == 0 ? Dsrc.cx : (b == 1 ? Dsrc.cc : (b == 2 ? Dsrc.cy : Dsrc.cs)));
     const double coff = (b == 0) ? offx : ((b == 2) ? offy : 0.0);
+    // (the set-up loops run over all NV entries with the unused terms
+    // selected away, so that each lane's loads are issued together; the
+    // sums keep their order)
     double zz = 0.0;
-    for (int j = kk; j < NV; ++j) zz += R[kk * NV + j] * (double(src[size_t(l) * NV + j]) - coff);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const double t = R[kk * NV + j] * (double(src[size_t(l) * NV + j]) - coff);
+      zz += j >= kk ? t : 0.0;
+    }
     zl = zz;
     vzd[axis * A2 + I] = zz;
     vz[axis * A2 + I] = T(zz);
     // lambda_z = R^-T lambda
     const T *glam = static_cast<const T *>(Dsrc.lam);
     double lz = 0.0;
-    for (int j = 0; j <= kk; ++j) lz += Rinv[j * NV + kk] * double(glam[size_t(l) * 4 * NV + b * NV + j]);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const double t = Rinv[j * NV + kk] * double(glam[size_t(l) * 4 * NV + b * NV + j]);
+      lz += j <= kk ? t : 0.0;
+    }
     lam = lz;
   }
   if (hrow) {
     const int kk = lane;
     const T *H2 = static_cast<const T *>(Dsrc.H2);
     double hsum = 0.0;
+#pragma unroll
     for (int e = 0; e < 6; ++e) hsum += double(H2[kk * 6 + e]) * Dsrc.bpsi[e];
     hpsi = T(hsum);
     const T *src = static_cast<const T *>(Dsrc.cpsi);
     double zz = 0.0;
-    for (int j = kk; j < NV; ++j) zz += R[kk * NV + j] * double(src[size_t(l) * NV + j]);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const double t = R[kk * NV + j] * double(src[size_t(l) * NV + j]);
+      zz += j >= kk ? t : 0.0;
+    }
     vzpsi[kk] = T(zz);
     const T *glp = static_cast<const T *>(Dsrc.lampsi);
     double lz = 0.0;
-    for (int j = 0; j <= kk; ++j) lz += Rinv[j * NV + kk] * double(glp[size_t(l) * NV + j]);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const double t = Rinv[j * NV + kk] * double(glp[size_t(l) * NV + j]);
+      lz += j <= kk ? t : 0.0;
+    }
     lampsi0 = T(lz);
     vaux[kk] = lampsi0;
   }
@@ -264,8 +284,10 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   if (prow) {
     const double *bb = axis == 0 ? Dsrc.bx : Dsrc.by;
     const double off = axis == 0 ? offx : offy;
+#pragma unroll
     for (int e = 0; e < 6; ++e) {
       double ae = 0.0;
+#pragma unroll
       for (int k = 0; k < NV; ++k) ae += Dsrc.Abc[e * NV + k] * vzd[axis * A2 + k];
       const double be = (e == 0 || e == 3) ? bb[e] - off : bb[e];
       bcc += Dsrc.H1d[I * 6 + e] * (ae - be);
@@ -561,6 +583,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // Q z, formed once in FP64 and then carried: Q z' = Q z + Q dz
   double qz = 0.0;
   if (prow && (qb == 0 || !(flags & AM_Q_CS_ZERO))) {
+#pragma unroll
     for (int k = 0; k < NV; ++k) qz += Dsrc.Qd[qi * NV + k] * vzd[axis * A2 + qb * NV + k];
   }
   project_reduce(false);
@@ -763,16 +786,24 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       const double coff = (b == 0) ? offx : ((b == 2) ? offy : 0.0);
       const int base = axis * A2 + (I >= NV ? NV : 0);
       double c = 0.0, lc = 0.0;
-      for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * vzd[base + j];
-      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * vwd[base + j];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        const double t = Rinv[kk * NV + j] * vzd[base + j], u = R[j * NV + kk] * vwd[base + j];
+        c += j >= kk ? t : 0.0;
+        lc += j <= kk ? u : 0.0;
+      }
       dst[size_t(l) * NV + kk] = T(c + coff);
       static_cast<T *>(Dsrc.lam)[size_t(l) * 4 * NV + b * NV + kk] = T(lc);
     }
     if (hrow) {
       const int kk = lane;
       double c = 0.0, lc = 0.0;
-      for (int j = kk; j < NV; ++j) c += Rinv[kk * NV + j] * double(vzpsi[j]);
-      for (int j = 0; j <= kk; ++j) lc += R[j * NV + kk] * double(vaux[2 * A2 + j]);
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        const double t = Rinv[kk * NV + j] * double(vzpsi[j]), u = R[j * NV + kk] * double(vaux[2 * A2 + j]);
+        c += j >= kk ? t : 0.0;
+        lc += j <= kk ? u : 0.0;
+      }
       static_cast<T *>(Dsrc.cpsi)[size_t(l) * NV + kk] = T(c);
       static_cast<T *>(Dsrc.lampsi)[size_t(l) * NV + kk] = T(lc);
     }
