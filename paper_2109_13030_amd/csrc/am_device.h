@@ -137,7 +137,8 @@ struct alignas(4 * sizeof(T)) Quad {
 struct FusedLds {
   int oxy;                 // obstacle centres, Pair [n][q]
   int op;                  // per-obstacle parameters [n][8] (OP_*)
-  int m1, gf;              // [2nv][2nv] operators M1 and N as Quad [a2/4][2nv]
+  int m1;                  // [2nv][2nv] operator M1 as Quad [a2/4][2nv]
+  int qrows;               // rows of Q = blockdiag(W^T W, W^T W or 0) as [2][nv][pad4(nv)]
   int xch;                 // [traj][half][kXchHalf] exchange area
   int wave0, wave_stride;  // per-wave areas
   int total;
@@ -177,7 +178,7 @@ __host__ __device__ inline FusedLds fused_layout(int q, int n, int nv, int tile,
   L.oxy = o; o += pad8(2 * n * q);
   L.op = o; o += 8 * n;
   L.m1 = o; o += a2 * 2 * nv;
-  L.gf = o; o += a2 * 2 * nv;
+  L.qrows = o; o += pad8(2 * nv * pad4(nv));
   L.xch = o; o += tile * 2 * kXchHalf;
   const WaveLds w = wave_layout(nv, red_rows, dw);
   L.wave_stride = pad8(w.red + red_rows * kRedRowStride);

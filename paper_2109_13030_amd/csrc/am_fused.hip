@@ -184,7 +184,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   const Quad<T> *opq = reinterpret_cast<const Quad<T> *>(lds + L.op);
   constexpr int QS = pad4(NV);   // row stride of the Q rows and block stride of dz
   static_assert(QS + NV <= A2, "both blocks of dz fit one axis's area");
-  const T *M1 = lds + L.m1, *QL = lds + L.gf;
+  const T *M1 = lds + L.m1, *QL = lds + L.qrows;
   const WaveLds wl = wave_layout(NV, RED, DW);
   T *wb = lds + L.wave0 + wave * L.wave_stride;
   T *vz = wb + wl.z, *vzpsi = wb + wl.zpsi, *vaux = wb + wl.aux;
@@ -304,7 +304,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // ---- per-lane trajectory values at t: positions (absolute, FP64) and
   // the other channels (T).  The positions are formed from the FP64
   // coefficients once and then carried: x' = x + U dz, the product of the
-  // small update in T added in FP64 (as N z above).
+  // small update in T added in FP64.
   double xa = 0.0, ya = 0.0;
   if (tv) {
 #pragma unroll
@@ -884,7 +884,7 @@ __device__ __forceinline__ void fused_block(const Desc &D) {
     const bool qcs = !(uni(D.flags) & AM_Q_CS_ZERO);
     for (int e = tid; e < 2 * NV * QS; e += blockDim.x) {
       const int bq = e / (NV * QS), rem = e % (NV * QS), i = rem / QS, k = rem % QS;
-      lds[L.gf + e] = (k < NV && (bq == 0 || qcs)) ? T(D.Qd[i * NV + k]) : T(0);
+      lds[L.qrows + e] = (k < NV && (bq == 0 || qcs)) ? T(D.Qd[i * NV + k]) : T(0);
     }
   }
   for (int i = tid; i < 2 * TILE * L.wave_stride; i += blockDim.x) lds[L.wave0 + i] = T(0);
