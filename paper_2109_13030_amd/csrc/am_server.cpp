@@ -35,6 +35,7 @@ namespace {
 using Clock = std::chrono::steady_clock;
 constexpr int kMaxStreams = 16;
 constexpr int kMaxPerLaunch = 256;
+constexpr size_t kPinnedArena = size_t(64) << 20;   // pinned host bytes for queued requests' input
 constexpr size_t kAlign = 256;
 
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -94,7 +95,15 @@ struct Request {
   int64_t ticket;
   am_handle *h;
   int client, B, K, q, nv, n;
-  std::vector<double> ox, oy, oa, ob, init;
+  // host input in the solve's precision, laid out as on the device: the
+  // obstacle table (x [n][q], y [n][q], a [n], b [n]) then the coefficients
+  // [5][B][nv]; written by the submitting thread into the server's pinned
+  // arena (copied to the device straight from there), or into in_vec when
+  // the arena is full
+  char *in = nullptr;
+  size_t in_off = 0, in_bytes = 0;
+  bool in_pinned = false;
+  std::vector<char> in_vec;
   am_problem prob;                 // scalars (device pointers filled at admission)
   Clock::time_point t_submit, t_done;
   bool done = false;
@@ -133,6 +142,11 @@ struct am_server {
   int device = 0;
   char *base = nullptr;
   Arena arena;
+  // pinned host arena for the requests' input (its own lock: submitting
+  // threads allocate, the scheduler releases at retirement)
+  char *pin_base = nullptr;
+  Arena pin_arena;
+  std::mutex pin_mu;
   std::vector<Slot> slots;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -152,6 +166,15 @@ struct am_server {
   std::map<std::string, am_handle *> kkt_cache;
 
   void *ptr(const Block &b) const { return base + b.off; }
+  void release_input(Request *r) {
+    if (r->in_pinned) {
+      std::lock_guard<std::mutex> lk(pin_mu);
+      pin_arena.release(r->in_off, r->in_bytes);
+      r->in_pinned = false;
+    }
+    r->in = nullptr;
+    std::vector<char>().swap(r->in_vec);
+  }
   bool alloc_evicting(size_t bytes, int keep_client, size_t *off);
   void run();
   bool admit(Slot &slot, std::vector<Request *> &batch);
@@ -253,10 +276,8 @@ bool am_server::admit(Slot &slot, std::vector<Request *> &batch) {
 int am_server::launch(Slot &slot) {
   // copies and the solve, all on the slot's stream (mu not held)
   const size_t es = elem_size(cfg.dtype);
-  const bool f64 = cfg.dtype == AM_F64;
   size_t need = 0;
-  for (Request *r : slot.reqs)
-    need += table_elems(r->n, r->q) * es + size_t(r->B) * 10 * r->nv * es + kBestElems * es;
+  for (Request *r : slot.reqs) need += (r->in_pinned ? 0 : r->in_bytes) + kBestElems * es;
   if (need > slot.pinned_bytes) {
     if (slot.pinned) (void)hipHostFree(slot.pinned);
     slot.pinned = nullptr;
@@ -270,20 +291,18 @@ int am_server::launch(Slot &slot) {
   std::vector<int32_t> bs, ks;
   std::vector<am_state> sts;
   for (Request *r : slot.reqs) {
-    // obstacle table -> device
     const size_t nq = size_t(r->n) * r->q;
+    const size_t tab = table_elems(r->n, r->q) * es, coef = size_t(r->B) * r->nv * es;
+    // the request's input goes to the device from the pinned arena, or
+    // through the slot's staging when it did not fit there
+    const char *src = r->in;
+    if (!r->in_pinned) {
+      std::memcpy(stage, r->in, r->in_bytes);
+      src = stage;
+      stage += r->in_bytes;
+    }
     char *tdev = base + r->table.off;
-    char *t0 = stage;
-    auto put = [&](const std::vector<double> &v) {
-      for (size_t i = 0; i < v.size(); ++i) {
-        if (f64) reinterpret_cast<double *>(stage)[i] = v[i];
-        else reinterpret_cast<float *>(stage)[i] = float(v[i]);
-      }
-      stage += v.size() * es;
-    };
-    put(r->ox); put(r->oy); put(r->oa); put(r->ob);
-    if (hipMemcpyAsync(tdev, t0, size_t(stage - t0), hipMemcpyHostToDevice, slot.stream) != hipSuccess)
-      return AM_ERR_HIP;
+    if (tab && hipMemcpyAsync(tdev, src, tab, hipMemcpyHostToDevice, slot.stream) != hipSuccess) return AM_ERR_HIP;
     am_problem p = r->prob;
     p.obs_x = tdev; p.obs_y = tdev + nq * es; p.obs_a = tdev + 2 * nq * es; p.obs_b = tdev + (2 * nq + r->n) * es;
     if (r->n == 0) p.obs_x = p.obs_y = p.obs_a = p.obs_b = nullptr;
@@ -291,31 +310,16 @@ int am_server::launch(Slot &slot) {
     // multipliers from the client's previous result (Sec. IV: lambda is
     // warm-started from the previous control loop), else zero
     const am_state st = state_of(this, r, r->state);
-    const size_t coef = size_t(r->B) * r->nv * es;
-    char *s0 = stage;
-    // [B][5][nv] doubles -> [5][B][nv] in the solve's precision
-    for (int v = 0; v < 5; ++v)
-      for (int l = 0; l < r->B; ++l) {
-        const double *src = r->init.data() + (size_t(l) * 5 + v) * r->nv;
-        if (f64) {
-          std::memcpy(stage, src, size_t(r->nv) * sizeof(double));
-        } else {
-          float *dst = reinterpret_cast<float *>(stage);
-          for (int k = 0; k < r->nv; ++k) dst[k] = float(src[k]);
-        }
-        stage += size_t(r->nv) * es;
-      }
+    if (hipMemcpyAsync(st.cx, src + tab, 5 * coef, hipMemcpyHostToDevice, slot.stream) != hipSuccess)
+      return AM_ERR_HIP;
     auto wit = r->warm_src;
+    // lambda [B][4nv] and lambda_psi [B][nv] are contiguous after the coefficients
     if (wit.live) {
-      if (hipMemcpyAsync(st.cx, s0, 5 * coef, hipMemcpyHostToDevice, slot.stream) != hipSuccess) return AM_ERR_HIP;
-      // lambda [B][4nv] and lambda_psi [B][nv] are contiguous after the coefficients
       if (hipMemcpyAsync(st.lam, base + wit.off + 5 * coef, 5 * coef, hipMemcpyDeviceToDevice, slot.stream) !=
           hipSuccess)
         return AM_ERR_HIP;
-    } else {
-      std::memset(stage, 0, 5 * coef);
-      stage += 5 * coef;
-      if (hipMemcpyAsync(st.cx, s0, 10 * coef, hipMemcpyHostToDevice, slot.stream) != hipSuccess) return AM_ERR_HIP;
+    } else if (hipMemsetAsync(st.lam, 0, 5 * coef, slot.stream) != hipSuccess) {
+      return AM_ERR_HIP;
     }
     am_state sr = st;
     if (cfg.select_best) sr.res = residuals_of(this, r, r->state);   // formed by the solve itself
@@ -380,6 +384,7 @@ void am_server::retire(Slot &slot) {
     }
     arena.release(r->table.off, r->table.bytes);
     if (r->work.live) arena.release(r->work.off, r->work.bytes);
+    release_input(r);
     client_busy.erase(r->client);
     ++completed;
   }
@@ -470,6 +475,11 @@ int am_server_create(const am_server_config *cfg, am_server **out) {
     return srv_fail(AM_ERR_NOMEM, "hipMalloc of the server budget failed");
   }
   s->arena.init(round_up(cfg->hbm_budget));
+  // (without the pinned arena every request goes through the slots' staging)
+  if (hipHostMalloc(reinterpret_cast<void **>(&s->pin_base), kPinnedArena) == hipSuccess)
+    s->pin_arena.init(kPinnedArena);
+  else
+    s->pin_base = nullptr;
   s->slots.resize(s->cfg.streams);
   for (int i = 0; i < s->cfg.streams; ++i) {
     Slot &sl = s->slots[i];
@@ -520,12 +530,7 @@ int am_server_submit(am_server *s, const am_request *r, int64_t *ticket) {
   if (n > 0 && (!r->obs_x || !r->obs_y || !r->obs_a || !r->obs_b))
     return srv_fail(AM_ERR_INVALID, "obstacle arrays are NULL");
   req->q = q; req->nv = nv; req->n = n;
-  req->ox.assign(r->obs_x, r->obs_x + size_t(n) * q);
-  req->oy.assign(r->obs_y, r->obs_y + size_t(n) * q);
-  req->oa.assign(r->obs_a, r->obs_a + n);
-  req->ob.assign(r->obs_b, r->obs_b + n);
   if (!r->init) return srv_fail(AM_ERR_INVALID, "request needs initial coefficients (init)");
-  req->init.assign(r->init, r->init + size_t(r->batch) * 5 * nv);
   std::memset(&req->prob, 0, sizeof req->prob);
   req->prob.r_circle = r->r_circle;
   for (int e = 0; e < 6; ++e) { req->prob.bc_x[e] = r->bc_x[e]; req->prob.bc_y[e] = r->bc_y[e]; req->prob.bc_psi[e] = r->bc_psi[e]; }
@@ -537,10 +542,45 @@ int am_server_submit(am_server *s, const am_request *r, int64_t *ticket) {
   const size_t need = round_up(state_elems(r->batch, nv, q) * es) + round_up(table_elems(n, q) * es) + round_up(wb);
   if (need > s->arena.capacity())
     return srv_fail(AM_ERR_INVALID, "request needs more device memory than the server budget");
+  {
+    // the input in the solve's precision and the device layout, written once
+    const bool f64 = s->cfg.dtype == AM_F64;
+    const size_t B = size_t(r->batch);
+    req->in_bytes = (table_elems(n, q) + B * 5 * nv) * es;
+    {
+      std::lock_guard<std::mutex> lk(s->pin_mu);
+      if (s->pin_base && s->pin_arena.alloc(req->in_bytes, &req->in_off)) {
+        req->in = s->pin_base + req->in_off;
+        req->in_pinned = true;
+      }
+    }
+    if (!req->in_pinned) {
+      req->in_vec.resize(req->in_bytes);
+      req->in = req->in_vec.data();
+    }
+    char *d = req->in;
+    auto put = [&](const double *src, size_t cnt) {
+      if (f64) std::memcpy(d, src, cnt * sizeof(double));
+      else {
+        float *f = reinterpret_cast<float *>(d);
+        for (size_t i = 0; i < cnt; ++i) f[i] = float(src[i]);
+      }
+      d += cnt * es;
+    };
+    if (n > 0) {
+      put(r->obs_x, size_t(n) * q); put(r->obs_y, size_t(n) * q); put(r->obs_a, n); put(r->obs_b, n);
+    }
+    // [B][5][nv] -> [5][B][nv]
+    for (int v = 0; v < 5; ++v)
+      for (size_t l = 0; l < B; ++l) put(r->init + (l * 5 + v) * nv, size_t(nv));
+  }
   req->t_submit = t_submit;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return srv_fail(AM_ERR_INVALID, "server is stopping");
+    if (s->stop) {
+      s->release_input(req.get());
+      return srv_fail(AM_ERR_INVALID, "server is stopping");
+    }
     req->ticket = s->next_ticket++;
     *ticket = req->ticket;
     s->pending.push_back(req.get());
@@ -617,6 +657,7 @@ void am_server_destroy(am_server *s) {
     if (sl.pinned) (void)hipHostFree(sl.pinned);
   }
   if (s->base) (void)hipFree(s->base);
+  if (s->pin_base) (void)hipHostFree(s->pin_base);
   for (auto &kv : s->kkt_cache) am_destroy(kv.second);
   delete s;
 }
