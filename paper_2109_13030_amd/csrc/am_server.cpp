@@ -329,6 +329,10 @@ int am_server::launch(Slot &slot) {
   if (cfg.mode == AM_SERVE_PLAIN) {
     Request *r = slot.reqs[0];
     rc = am_solve_batch_plain(r->h, &ps[0], r->B, r->K, &sts[0], base + r->work.off, r->work.bytes, slot.stream);
+  } else if (hs.size() == 1) {
+    // one request: the single-problem launch (descriptor as a kernel
+    // argument, no table copy); bit-identical to its multi-problem form
+    rc = am_solve_batch(hs[0], &ps[0], bs[0], ks[0], &sts[0], slot.stream);
   } else {
     rc = am_solve_multi(int32_t(hs.size()), hs.data(), ps.data(), bs.data(), ks.data(), sts.data(),
                         base + slot.desc.off, slot.desc.bytes, slot.stream);
