@@ -324,3 +324,40 @@ def test_server_kkt_cache_by_shape(am):
         am.solve(h, p, ds, K)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(ds.t["traj"].cpu().numpy(), traj)
+
+
+def test_inputs_beyond_the_pinned_arena(am):
+    """More queued input than the server's pinned host arena holds (64 MiB):
+    the requests that do not fit go through the launch slot's staging, and
+    every result still equals its direct solve (first, middle and last
+    request checked)."""
+    import torch
+    c = inputs.serving_clients(1, seed=91)[0]
+    B = 2048
+    pb = c["problem"]
+    init = inputs.make_initial(pb, B, 91, 0.5)
+    h = am.Handle.for_problem(pb, "f32")
+    per = (2 * len(pb["oa"]) * pb["q"] + 2 * len(pb["oa"]) + 5 * B * pb["nv"]) * 4
+    count = (64 << 20) // per + 12
+    K = 2
+    srv = am.Server(1 << 31, streams=1, max_per_launch=64, idle_spin_us=2000)
+    # a long request holds the only stream while the rest queue up, so their
+    # inputs are all staged before any of them launches
+    blocker = srv.submit(h, pb, 100000, 256, 40000, {k: v[:256] for k, v in init.items()})
+    tickets = [srv.submit(h, pb, i, B, K, init) for i in range(count)]
+    assert srv.wait(blocker, 120.0)[0]
+    outs = {}
+    for i, t in enumerate(tickets):
+        done, _, tr = srv.wait(t, 120.0, traj=i in (0, count // 2, count - 1))
+        assert done
+        if tr is not None:
+            outs[i] = tr
+    assert srv.stats()["completed"] == count + 1
+    srv.close()
+    p = am.DeviceProblem(pb, "f32")
+    ds = am.DeviceState(init, len(pb["r"]), len(pb["oa"]), pb["q"], "f32")
+    am.solve(h, p, ds, K)
+    torch.cuda.synchronize()
+    ref = ds.t["traj"].cpu().numpy()
+    for i, tr in outs.items():
+        np.testing.assert_array_equal(tr, ref, err_msg=f"request {i}")
