@@ -195,13 +195,14 @@ def run_gpu(args):
 
 
 def run_serving(rates, n_requests, modes=("continuous", "plain"), n_clients: int = 32,
-                saturation: int = 64, budget: int = 4 << 30, seed: int = 5, max_rate=None, streams: int = 4):
+                saturation: int = 64, budget: int = 4 << 30, seed: int = 5, max_rate=None, streams: int = 2):
     """Replanning workload c5 through the continuous-batching server: Poisson
     arrivals, per request B ~ U{256..2048}, n ~ U{5..30} moving obstacles,
     5 circles, 20 warm-started AM iterations.  Latency = completion seen by
     the server's scheduler - submission.  Modes: continuous batching (all
-    admissible pending requests of one shape per launch, several launches in
-    flight), sequential (the same fused kernel, one request per launch, one
+    admissible pending requests of one shape per launch, up to `streams`
+    launches in flight: two measured best against one and four, at 2-3 kHz
+    and in bursts), sequential (the same fused kernel, one request per launch, one
     launch at a time) and plain (one request at a time on the per-sub-step
     path).  max_rate[mode] skips the rates a mode cannot sustain.  Also a
     saturation run (all requests submitted at once) for capacity."""

@@ -381,7 +381,7 @@ def select_best(h: Handle, res, fc_tol: float, stream=None):
 class Server:
     """Continuous-batching replanning server (am_server_*)."""
 
-    def __init__(self, hbm_budget: int, streams: int = 4, max_per_launch: int = 64,
+    def __init__(self, hbm_budget: int, streams: int = 2, max_per_launch: int = 64,
                  mode: int = SERVE_CONTINUOUS, dtype: str = "f32", select_best: bool = False,
                  fc_tol: float = 0.05, idle_spin_us: int = 0):
         c = ServerConfig()
