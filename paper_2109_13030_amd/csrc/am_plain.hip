@@ -583,51 +583,67 @@ __device__ __forceinline__ void split_bf16(const float (&v)[4], bf16x4 &hi, bf16
   }
 }
 
+// Block (x, g) holds four tiles of 16 trajectories and output group g
+// (0: x position rows [V W U], 1: x slack rows U, 2, 3: the same for y, 4:
+// heading rows U); the group's basis fragments, split once per block, are
+// shared by the four wavefronts through LDS.
+constexpr int kMfmaMaxK = (AM_MAX_Q + 15) / 16;   // K steps of 16 time steps
+
 template <int NV>
-__global__ void k_contract_mfma(Desc D, Ptrs<float> w) {
+__global__ __launch_bounds__(256) void k_contract_mfma(Desc D, Ptrs<float> w) {
   static_assert(NV <= 16, "one 16-wide output tile per group");
-  const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  const int l0 = tile * 16;
-  if (l0 >= D.B) return;
+  __shared__ bf16x4 frag[3][kMfmaMaxK][64][2];   // [basis of the group][k step][lane][hi, lo]
+  const int lane = threadIdx.x & 63, g = blockIdx.y;
   const int q = D.q, B = D.B;
   const int r = lane & 15, kq = lane >> 4;     // A row / B column; k quad
-  const int la = l0 + r;                        // trajectory of this lane's A row
+  const int ksteps = (q + 15) / 16;
   const float *U = static_cast<const float *>(D.U), *V = static_cast<const float *>(D.V),
               *W = static_cast<const float *>(D.W);
-  // groups: (channel, basis) pairs, basis 0 = U, 1 = V, 2 = W
+  // (channel, basis) pairs of the group, basis 0 = U, 1 = V, 2 = W
   const int g_ch[5][3] = {{0, 1, 2}, {3, -1, -1}, {4, 5, 6}, {7, -1, -1}, {8, -1, -1}};
   const int g_bs[5][3] = {{1, 2, 0}, {0, -1, -1}, {1, 2, 0}, {0, -1, -1}, {0, -1, -1}};
-  const int ksteps = (q + 15) / 16;
-  for (int g = 0; g < 5; ++g) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int e = 0; e < 3; ++e) {
-      const int c = g_ch[g][e];
-      if (c < 0) break;
-      const float *basis = g_bs[g][e] == 0 ? U : (g_bs[g][e] == 1 ? V : W);
-      const float *ch = w.chan + size_t(la < B ? la : 0) * 9 * q + size_t(c) * q;
-      for (int ks = 0; ks < ksteps; ++ks) {
-        const int t0 = ks * 16 + kq * 4;
-        float av[4], bv[4];
+  const int ne = g_ch[g][1] < 0 ? 1 : 3;
+  // B fragments: lane L holds B[k 4(L/16)..+3][out L%16] of every k step
+  for (int i = threadIdx.x; i < ne * ksteps * 64; i += blockDim.x) {
+    const int e = i / (ksteps * 64), rem = i % (ksteps * 64), ks = rem / 64, ln = rem % 64;
+    const float *basis = g_bs[g][e] == 0 ? U : (g_bs[g][e] == 1 ? V : W);
+    const int rr = ln & 15, t0 = ks * 16 + (ln >> 4) * 4;
+    float bv[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int t = t0 + i;
-          av[i] = (la < B && t < q) ? ch[t] : 0.f;
-          bv[i] = (r < NV && t < q) ? basis[t * NV + r] : 0.f;
-        }
-        bf16x4 ah, al, bh, bl;
-        split_bf16(av, ah, al);
-        split_bf16(bv, bh, bl);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    for (int j = 0; j < 4; ++j) bv[j] = (rr < NV && t0 + j < q) ? basis[(t0 + j) * NV + rr] : 0.f;
+    split_bf16(bv, frag[e][ks][ln][0], frag[e][ks][ln][1]);
+  }
+  __syncthreads();
+  const int l0 = (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * 16;
+  if (l0 >= B) return;
+  const int la = l0 + r;                        // trajectory of this lane's A row
+  const bool vec = (q % 4) == 0;                // rows of 4 time steps are 16-byte aligned
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int e = 0; e < ne; ++e) {
+    const float *ch = w.chan + size_t(la < B ? la : 0) * 9 * q + size_t(g_ch[g][e]) * q;
+    for (int ks = 0; ks < ksteps; ++ks) {
+      const int t0 = ks * 16 + kq * 4;
+      float av[4];
+      if (vec && t0 < q) {
+        const float4 v4 = *reinterpret_cast<const float4 *>(ch + t0);
+        av[0] = v4.x; av[1] = v4.y; av[2] = v4.z; av[3] = v4.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = t0 + i < q ? ch[t0 + i] : 0.f;
       }
+      if (la >= B) av[0] = av[1] = av[2] = av[3] = 0.f;
+      bf16x4 ah, al;
+      split_bf16(av, ah, al);
+      const bf16x4 bh = frag[e][ks][lane][0], bl = frag[e][ks][lane][1];
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
     }
+  }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int lt = l0 + kq * 4 + i;
-      if (lt < B && r < NV) w.tot[size_t(lt) * 5 * NV + g * NV + r] = acc[i];
-    }
+  for (int i = 0; i < 4; ++i) {
+    const int lt = l0 + kq * 4 + i;
+    if (lt < B && r < NV) w.tot[size_t(lt) * 5 * NV + g * NV + r] = acc[i];
   }
 }
 
@@ -701,7 +717,7 @@ void contract(const Desc &D, const Ptrs<T> &w, hipStream_t st, int update) {
   if constexpr (sizeof(T) == 4) {
     if (D.flags & AM_PLAIN_BF16X3) {
       const int tiles = (D.B + 15) / 16;
-      hipLaunchKernelGGL((k_contract_mfma<NV>), dim3((tiles + 3) / 4), dim3(kThreads), 0, st, D, w);
+      hipLaunchKernelGGL((k_contract_mfma<NV>), dim3((tiles + 3) / 4, 5), dim3(256), 0, st, D, w);
       hipLaunchKernelGGL((k_update<T, NV>), dim3(blocks_for(size_t(D.B) * 5 * NV)), dim3(kThreads), 0, st, D, w,
                          update);
       return;
