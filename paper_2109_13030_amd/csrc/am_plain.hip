@@ -603,15 +603,31 @@ __global__ __launch_bounds__(256) void k_contract_mfma(Desc D, Ptrs<float> w) {
   const int g_ch[5][3] = {{0, 1, 2}, {3, -1, -1}, {4, 5, 6}, {7, -1, -1}, {8, -1, -1}};
   const int g_bs[5][3] = {{1, 2, 0}, {0, -1, -1}, {1, 2, 0}, {0, -1, -1}, {0, -1, -1}};
   const int ne = g_ch[g][1] < 0 ? 1 : 3;
-  // B fragments: lane L holds B[k 4(L/16)..+3][out L%16] of every k step
-  for (int i = threadIdx.x; i < ne * ksteps * 64; i += blockDim.x) {
-    const int e = i / (ksteps * 64), rem = i % (ksteps * 64), ks = rem / 64, ln = rem % 64;
-    const float *basis = g_bs[g][e] == 0 ? U : (g_bs[g][e] == 1 ? V : W);
-    const int rr = ln & 15, t0 = ks * 16 + (ln >> 4) * 4;
-    float bv[4];
+  // B fragments: lane L holds B[k 4(L/16)..+3][out L%16] of every k step;
+  // a thread's entries (at most kFragPer) are all loaded before any is
+  // split, so one memory latency covers them
+  constexpr int kFragPer = (3 * kMfmaMaxK * 64 + 255) / 256;
+  {
+    const int total = ne * ksteps * 64;
+    float bv[kFragPer][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bv[j] = (rr < NV && t0 + j < q) ? basis[(t0 + j) * NV + rr] : 0.f;
-    split_bf16(bv, frag[e][ks][ln][0], frag[e][ks][ln][1]);
+    for (int u = 0; u < kFragPer; ++u) {
+      const int i = threadIdx.x + u * 256;
+      const int e = i / (ksteps * 64), rem = i % (ksteps * 64), ks = rem / 64, ln = rem % 64;
+      const float *basis = g_bs[g][e < ne ? e : 0] == 0 ? U : (g_bs[g][e < ne ? e : 0] == 1 ? V : W);
+      const int rr = ln & 15, t0 = ks * 16 + (ln >> 4) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bv[u][j] = (i < total && rr < NV && t0 + j < q) ? basis[(t0 + j) * NV + rr] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kFragPer; ++u) {
+      const int i = threadIdx.x + u * 256;
+      if (i < total) {
+        const int e = i / (ksteps * 64), rem = i % (ksteps * 64), ks = rem / 64, ln = rem % 64;
+        split_bf16(bv[u], frag[e][ks][ln][0], frag[e][ks][ln][1]);
+      }
+    }
   }
   __syncthreads();
   const int l0 = (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * 16;
