@@ -91,6 +91,17 @@ __device__ __forceinline__ double lane_xor1(double v) {
   return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
 }
 
+// Value of lane ^ 2 (DPP quad permutation [2, 3, 0, 1]).
+__device__ __forceinline__ float lane_xor2(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double lane_xor2(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp(int(b & 0xffffffffLL), 0x4E, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), 0x4E, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
+}
+
 // Sums over the 64 lanes of G per-lane partials, in passes of ROWS rows.
 // Lane pairs are added with DPP, the 32 pair sums of partial g go to LDS row
 // g (even lanes write row g, odd lanes row g+1, so every lane stores), and
@@ -132,6 +143,46 @@ __device__ __forceinline__ T wave_sum_many(const T (&p)[G], T *red, int lane) {
     }
     wave_sync();
   }
+  return s;
+}
+
+// The same for a few rows (the heading sums): a second DPP level before
+// LDS, lanes of a quad exchanging their rows, so lane L keeps row
+// 4i + L % 4 of pair-register i summed over its quad and an LDS row holds 16
+// quad sums (half the stores and loads, fewer adds).  On return lane g
+// (g < G) holds the total of partial g.
+template <typename T, int G>
+__device__ __forceinline__ T wave_sum_quad(const T (&p)[G], T *red, int lane) {
+#pragma clang fp contract(off)
+  constexpr int G1 = (G + 1) / 2, G2 = (G1 + 1) / 2;
+  static_assert(4 * G2 <= kRedRows / 2, "rows of one pass");
+  const bool odd = lane & 1, hi2 = lane & 2;
+  T r1[G1];
+#pragma unroll
+  for (int j = 0; j < G1; ++j) {
+    const T a = p[2 * j] + lane_xor1(p[2 * j]);
+    const T b = 2 * j + 1 < G ? p[2 * j + 1] + lane_xor1(p[2 * j + 1]) : T(0);
+    r1[j] = odd ? b : a;
+  }
+#pragma unroll
+  for (int i = 0; i < G2; ++i) {
+    const T c = r1[2 * i] + lane_xor2(r1[2 * i]);
+    const T d = 2 * i + 1 < G1 ? r1[2 * i + 1] + lane_xor2(r1[2 * i + 1]) : T(0);
+    red[(4 * i + (lane & 3)) * kRedRowStride + (lane >> 2)] = hi2 ? d : c;
+  }
+  wave_sync();
+  T s = T(0);
+  if (lane < G) {
+    const Quad<T> *row = reinterpret_cast<const Quad<T> *>(red + lane * kRedRowStride);
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const Quad<T> v = row[c];
+      s0 += v.a; s1 += v.b; s2 += v.c; s3 += v.d;
+    }
+    s = (s0 + s1) + (s2 + s3);
+  }
+  wave_sync();
   return s;
 }
 
@@ -626,7 +677,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 #pragma unroll
     for (int k = 0; k < NV; ++k) pp[k] = Ut[k] * dpsi;
     __builtin_amdgcn_s_setprio(2);
-    const T upsi = wave_sum_many<T, NV, RED>(pp, red, lane);
+    const T upsi = wave_sum_quad<T, NV>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = upsi;
     __syncthreads();
     if (hrow) {
@@ -654,7 +705,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     T pp[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) pp[k] = Ub[k] * racc;
-    const T s = wave_sum_many<T, NV, RED>(pp, red, lane);
+    const T s = wave_sum_quad<T, NV>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = s;
     __syncthreads();
     if (hrow) vaux[2 * A2 + lane] = lampsi0 - rhop * exchange_sum(kXchBig + lane);
