@@ -114,7 +114,7 @@ constexpr int kXchBig = 64;
 constexpr int kXchSmall = 16;
 constexpr int kXchHalf = kXchBig + kXchSmall;
 
-// Reduction scratch: up to kRedRows rows of 32 lane-pair sums (a launch
+// Reduction scratch: up to kRedRows rows of 16 lane-quad sums (a launch
 // built for 3 wavefronts per SIMD reduces in passes of kRedRows / 2 rows to
 // halve the area).
 constexpr int kRedRows = 56;

@@ -102,60 +102,21 @@ __device__ __forceinline__ double lane_xor2(double v) {
   return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
 }
 
-// Sums over the 64 lanes of G per-lane partials, in passes of ROWS rows.
-// Lane pairs are added with DPP, the 32 pair sums of partial g go to LDS row
-// g (even lanes write row g, odd lanes row g+1, so every lane stores), and
-// lane g adds its row with four interleaved accumulators.  On return lane g
-// (g < G) holds the total of partial g; the passes do not change the order
-// of any addition.
+// Sums over the 64 lanes of G per-lane partials.  Two DPP levels first:
+// lane pairs add (odd lanes keeping the odd row of each register pair), then
+// quads exchange (lanes with bit 1 set keeping the second pair-register), so
+// lane L holds row 4i + L % 4 of quad register i summed over its quad; the
+// 16 quad sums of a row go to LDS and lane g adds row g with four
+// interleaved accumulators.  Rows go through LDS in passes of ROWS (a
+// multiple of 4).  On return lane g (g < G) holds the total of partial g;
+// the passes do not change the order of any addition.  (A plain add takes
+// the neighbour through its DPP operand, one instruction; fused into the
+// caller's product it would need a separate DPP move and the product twice.)
 template <typename T, int G, int ROWS>
-__device__ __forceinline__ T wave_sum_many(const T (&p)[G], T *red, int lane) {
-  // A plain add takes the neighbour through its DPP operand (one
-  // instruction); fused into the caller's product it would need a separate
-  // DPP move and the product twice.
-#pragma clang fp contract(off)
-  static_assert(ROWS <= kRedRows && ROWS % 2 == 0, "rows per pass");
-  const int odd = lane & 1, col = lane >> 1;
-  T s = T(0);
-#pragma unroll
-  for (int g0 = 0; g0 < G; g0 += ROWS) {
-    const int end = g0 + ROWS < G ? g0 + ROWS : G;
-#pragma unroll
-    for (int k = g0; k < G && k < g0 + ROWS; k += 2) {
-      const T a = p[k] + lane_xor1(p[k]);
-      if (k + 1 < end) {
-        const T b = p[k + 1] + lane_xor1(p[k + 1]);
-        red[(k - g0 + odd) * kRedRowStride + col] = odd ? b : a;
-      } else if (!odd) {
-        red[(k - g0) * kRedRowStride + col] = a;
-      }
-    }
-    wave_sync();
-    if (lane >= g0 && lane < end) {
-      const Quad<T> *row = reinterpret_cast<const Quad<T> *>(red + (lane - g0) * kRedRowStride);
-      T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const Quad<T> v = row[c];
-        s0 += v.a; s1 += v.b; s2 += v.c; s3 += v.d;
-      }
-      s = (s0 + s1) + (s2 + s3);
-    }
-    wave_sync();
-  }
-  return s;
-}
-
-// The same for a few rows (the heading sums): a second DPP level before
-// LDS, lanes of a quad exchanging their rows, so lane L keeps row
-// 4i + L % 4 of pair-register i summed over its quad and an LDS row holds 16
-// quad sums (half the stores and loads, fewer adds).  On return lane g
-// (g < G) holds the total of partial g.
-template <typename T, int G>
 __device__ __forceinline__ T wave_sum_quad(const T (&p)[G], T *red, int lane) {
 #pragma clang fp contract(off)
-  constexpr int G1 = (G + 1) / 2, G2 = (G1 + 1) / 2;
-  static_assert(4 * G2 <= kRedRows / 2, "rows of one pass");
+  constexpr int G1 = (G + 1) / 2, G2 = (G1 + 1) / 2, RPP = ROWS / 4;   // quad registers per pass
+  static_assert(ROWS <= kRedRows && ROWS % 4 == 0, "rows per pass");
   const bool odd = lane & 1, hi2 = lane & 2;
   T r1[G1];
 #pragma unroll
@@ -164,25 +125,29 @@ __device__ __forceinline__ T wave_sum_quad(const T (&p)[G], T *red, int lane) {
     const T b = 2 * j + 1 < G ? p[2 * j + 1] + lane_xor1(p[2 * j + 1]) : T(0);
     r1[j] = odd ? b : a;
   }
-#pragma unroll
-  for (int i = 0; i < G2; ++i) {
-    const T c = r1[2 * i] + lane_xor2(r1[2 * i]);
-    const T d = 2 * i + 1 < G1 ? r1[2 * i + 1] + lane_xor2(r1[2 * i + 1]) : T(0);
-    red[(4 * i + (lane & 3)) * kRedRowStride + (lane >> 2)] = hi2 ? d : c;
-  }
-  wave_sync();
   T s = T(0);
-  if (lane < G) {
-    const Quad<T> *row = reinterpret_cast<const Quad<T> *>(red + lane * kRedRowStride);
-    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const Quad<T> v = row[c];
-      s0 += v.a; s1 += v.b; s2 += v.c; s3 += v.d;
+  for (int i0 = 0; i0 < G2; i0 += RPP) {
+#pragma unroll
+    for (int i = i0; i < G2 && i < i0 + RPP; ++i) {
+      const T c = r1[2 * i] + lane_xor2(r1[2 * i]);
+      const T d = 2 * i + 1 < G1 ? r1[2 * i + 1] + lane_xor2(r1[2 * i + 1]) : T(0);
+      red[(4 * (i - i0) + (lane & 3)) * kRedRowStride + (lane >> 2)] = hi2 ? d : c;
     }
-    s = (s0 + s1) + (s2 + s3);
+    wave_sync();
+    const int g0 = 4 * i0;
+    if (lane >= g0 && lane < G && lane < g0 + ROWS) {
+      const Quad<T> *row = reinterpret_cast<const Quad<T> *>(red + (lane - g0) * kRedRowStride);
+      T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const Quad<T> v = row[c];
+        s0 += v.a; s1 += v.b; s2 += v.c; s3 += v.d;
+      }
+      s = (s0 + s1) + (s2 + s3);
+    }
+    wave_sync();
   }
-  wave_sync();
   return s;
 }
 
@@ -600,7 +565,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     // the reduction and exchange are the pair's critical path: while a wave
     // is in them the SIMD issues its instructions first
     __builtin_amdgcn_s_setprio(2);
-    const T tot = wave_sum_many<T, G, RED>(pr, red, lane);
+    const T tot = wave_sum_quad<T, G, RED>(pr, red, lane);
     if (lane < G) xmine[lane] = tot;
     __syncthreads();
     if (prow) tr = exchange_sum(lane);
@@ -677,7 +642,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 #pragma unroll
     for (int k = 0; k < NV; ++k) pp[k] = Ut[k] * dpsi;
     __builtin_amdgcn_s_setprio(2);
-    const T upsi = wave_sum_quad<T, NV>(pp, red, lane);
+    const T upsi = wave_sum_quad<T, NV, RED>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = upsi;
     __syncthreads();
     if (hrow) {
@@ -705,7 +670,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     T pp[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) pp[k] = Ub[k] * racc;
-    const T s = wave_sum_quad<T, NV>(pp, red, lane);
+    const T s = wave_sum_quad<T, NV, RED>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = s;
     __syncthreads();
     if (hrow) vaux[2 * A2 + lane] = lampsi0 - rhop * exchange_sum(kXchBig + lane);
