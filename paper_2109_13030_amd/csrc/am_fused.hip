@@ -576,9 +576,32 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   eval_xy(false);
   eval_psi();
   psih = psi;
-  // row I of M1 (position block), read from LDS in every product (in
-  // registers it would push the kernel past its register budget)
-  auto m1_dot = [&](const T *v) { return row_dot<T, NV>(M1, I, v); };
+  // row I of M1 (position block) in registers for the whole solve (WAVES =
+  // 2 budget; the three-wavefront build reads it from LDS in every product)
+  constexpr int M1Q = pad4(N2) / 4;
+  Quad<T> m1r[RED == kRedRows ? M1Q : 1];
+  if constexpr (RED == kRedRows) {
+    const Quad<T> *o = reinterpret_cast<const Quad<T> *>(M1);
+#pragma unroll
+    for (int c = 0; c < M1Q; ++c) m1r[c] = o[c * N2 + I];
+  }
+  auto m1_dot = [&](const T *v) -> T {
+    if constexpr (RED == kRedRows) {
+      const Quad<T> *vv = reinterpret_cast<const Quad<T> *>(v);
+      T acc0 = T(0), acc1 = T(0);
+#pragma unroll
+      for (int c = 0; c < M1Q; ++c) {
+        const Quad<T> x = vv[c];
+        acc0 += m1r[c].a * x.a;
+        acc1 += m1r[c].b * x.b;
+        if (4 * c + 2 < N2) acc0 += m1r[c].c * x.c;
+        if (4 * c + 3 < N2) acc1 += m1r[c].d * x.d;
+      }
+      return acc0 + acc1;
+    } else {
+      return row_dot<T, NV>(M1, I, v);
+    }
+  };
   // row I of Q = blockdiag(W^T W, W^T W or 0) times the block of dz it
   // meets (dz is stored with its blocks QS apart; the padding reads zero)
   const int qb = I / NV, qi = I - qb * NV;
