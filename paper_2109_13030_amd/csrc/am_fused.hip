@@ -605,13 +605,23 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // row I of Q = blockdiag(W^T W, W^T W or 0) times the block of dz it
   // meets (dz is stored with its blocks QS apart; the padding reads zero)
   const int qb = I / NV, qi = I - qb * NV;
+  // (in registers under the two-wavefront budget, like the M1 row)
+  Quad<T> qr[RED == kRedRows ? QS / 4 : 1];
+  if constexpr (RED == kRedRows) {
+    const Quad<T> *o = reinterpret_cast<const Quad<T> *>(QL + (qb * NV + qi) * QS);
+#pragma unroll
+    for (int c = 0; c < QS / 4; ++c) qr[c] = o[c];
+  }
   auto q_dot = [&]() {
     const Quad<T> *o = reinterpret_cast<const Quad<T> *>(QL + (qb * NV + qi) * QS);
     const Quad<T> *v = reinterpret_cast<const Quad<T> *>(vdz + axis * A2 + qb * QS);
     T acc0 = T(0), acc1 = T(0);
 #pragma unroll
     for (int c = 0; c < QS / 4; ++c) {
-      const Quad<T> a = o[c], b = v[c];
+      Quad<T> a;
+      if constexpr (RED == kRedRows) a = qr[c];
+      else a = o[c];
+      const Quad<T> b = v[c];
       acc0 += a.a * b.a;
       acc1 += a.b * b.b;
       acc0 += a.c * b.c;
