@@ -285,6 +285,7 @@ int am_setup(const am_shape *s, am_handle **out) {
     amk::Desc *tbl = nullptr;
     if ((e = amk::static_table(h->device, &tbl)) != hipSuccess) rc = hip_fail(e, "static problem table");
   }
+  if (rc == AM_OK && (e = amk::preload_kernels()) != hipSuccess) rc = hip_fail(e, "kernel load");
   if (rc != AM_OK) {
     am_destroy(h);
     return rc;

@@ -81,6 +81,9 @@ hipError_t launch_select_best(const void *res, int B, double tol, int32_t *idx, 
 hipError_t launch_residuals(const Desc &d, const void *P, const void *Pd, const void *Pdd, void *out,
                             bool f64, int nv, hipStream_t st);
 hipError_t launch_desc_copy(const Desc *host_descs, int count, Desc *dev_dst, hipStream_t st);
+// Loads the kernels of the residual/selection/descriptor-copy source file
+// (otherwise loaded by the first launch of one of them).
+hipError_t preload_kernels();
 // Device address of `device`'s copy of the static problem table
 // (AM_STATIC_MAX_PROBLEMS descriptors); `device` must be current on the
 // first call for it.

@@ -493,6 +493,13 @@ int am_server_create(const am_server_config *cfg, am_server **out) {
       am_server_destroy(s);
       return srv_fail(AM_ERR_HIP, "stream/event creation failed");
     }
+    // a first operation on each stream, so that the runtime binds it to a
+    // hardware queue now and not during the first request that overlaps
+    // another (that first use costs milliseconds)
+    if (hipMemsetAsync(s->base, 0, kAlign, sl.stream) != hipSuccess || hipStreamSynchronize(sl.stream) != hipSuccess) {
+      am_server_destroy(s);
+      return srv_fail(AM_ERR_HIP, "stream warm-up failed");
+    }
   }
   s->worker = std::thread([s] { s->run(); });
   *out = s;
