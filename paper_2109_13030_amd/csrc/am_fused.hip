@@ -335,26 +335,32 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   T xd, xdd, cc, yd, ydd, ss, psi, cps, sps, psih;
   T racc = T(0);   // sum over the iterations of psi_sign (psi - psi_hat) at t
 
-  // derivatives and slack channels from z; positions advanced by dz when
-  // `step` is set
+  // derivative and slack channels from the initial z (first call), then
+  // every channel advanced by the product of the update dz (its blocks QS
+  // apart in LDS), the positions in FP64
   auto eval_xy = [&](bool step) {
     T a0 = 0, b0 = 0, a1 = 0, a2 = 0, a3 = 0, b1 = 0, b2 = 0, b3 = 0;
+    if (!step) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const T zx = vz[k], zc = vz[NV + k], zy = vz[A2 + k], zs = vz[A2 + NV + k];
+        a1 += Vb[k] * zx; a2 += Wb[k] * zx; a3 += Ub[k] * zc;
+        b1 += Vb[k] * zy; b2 += Wb[k] * zy; b3 += Ub[k] * zs;
+      }
+      xd = a1; xdd = a2; cc = a3;
+      yd = b1; ydd = b2; ss = b3;
+      return;
+    }
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      const T zx = vz[k], zc = vz[NV + k], zy = vz[A2 + k], zs = vz[A2 + NV + k];
-      if (step) {
-        a0 += Ub[k] * vdz[k];
-        b0 += Ub[k] * vdz[A2 + k];
-      }
-      a1 += Vb[k] * zx; a2 += Wb[k] * zx; a3 += Ub[k] * zc;
-      b1 += Vb[k] * zy; b2 += Wb[k] * zy; b3 += Ub[k] * zs;
+      const T dx = vdz[k], dc = vdz[QS + k], dy = vdz[A2 + k], ds = vdz[A2 + QS + k];
+      a0 += Ub[k] * dx; a1 += Vb[k] * dx; a2 += Wb[k] * dx; a3 += Ub[k] * dc;
+      b0 += Ub[k] * dy; b1 += Vb[k] * dy; b2 += Wb[k] * dy; b3 += Ub[k] * ds;
     }
-    if (step) {
-      xa += double(a0);
-      ya += double(b0);
-    }
-    xd = a1; xdd = a2; cc = a3;
-    yd = b1; ydd = b2; ss = b3;
+    xa += double(a0);
+    ya += double(b0);
+    xd += a1; xdd += a2; cc += a3;
+    yd += b1; ydd += b2; ss += b3;
   };
   // offset of this lane's robot centre from an obstacle centre, formed in
   // FP64 and rounded once
@@ -650,10 +656,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const double dz = double(m1_dot(vw + axis * A2)) - bcc;
     bcc = 0.0;
     zl += dz;
-    if (prow) {
-      vz[axis * A2 + I] = T(zl);
-      vdz[axis * A2 + qb * QS + qi] = T(dz);
-    }
+    if (prow) vdz[axis * A2 + qb * QS + qi] = T(dz);
     wave_sync();
     eval_xy(true);
 
