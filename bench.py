@@ -62,17 +62,31 @@ def plain_bytes_per_iter(q: int, nv: int, m: int, n: int, B: int, esize: int = 4
     return float(B) * (16 * m * n * q + 2 * (8 + 3 + 1 + 4 + 9) * q * esize)
 
 
+# Files the fused kernel is compiled from; counters taken on an older build
+# of any of them no longer describe the kernel.
+FUSED_SOURCES = ["paper_2109_13030_amd/csrc/am_fused.hip", "paper_2109_13030_amd/csrc/am_device.h",
+                 "paper_2109_13030_amd/csrc/am_internal.h", "paper_2109_13030_amd/csrc/am_poly.h",
+                 "include/am.h"]
+
+
+def kernel_sources_sha256(sources) -> str:
+    """SHA-256 over the concatenated bytes of the given repository files."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in sources:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload: str):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE runs (scaled by the copy-kernel reference), or None
     when the kernel source has changed since they were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"fused_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    if kernel_sources_sha256(rec["sources"]) != rec["sources_sha256"]:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -81,13 +95,11 @@ def measured_valu(workload: str):
     """VALU wave-instructions per launch of the fused kernel from the
     committed rocprofv3 SQ_INSTS_VALU run, or None when the kernel source has
     changed since."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"fused_{workload}_valu.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    if kernel_sources_sha256(rec["sources"]) != rec["sources_sha256"]:
         return None
     return rec["sq_insts_valu_per_launch"]
 
