@@ -54,6 +54,7 @@
 #include <hip/hip_runtime.h>
 
 #include <limits>
+#include <type_traits>
 
 #include "am_device.h"
 #include "am_internal.h"
@@ -383,19 +384,51 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // Projection of one obstacle's rows at this lane's t for every circle
   // (fast form; a non-finite sum, as from a zero or subnormal r2, is redone
   // element by element afterwards).
-  // p = (a^2, b^2, ab, max(a, b)) of the inflated ellipse.
+  // p = (a^2, b^2, ab, max(a, b)) of the inflated ellipse.  The offset of
+  // circle i from the obstacle centre is (xh - o.x) + (xl + r_i u): the
+  // position split into its FP32 rounding xh and the remainder xl, so the
+  // per-obstacle difference is one FP32 subtraction and the remainder joins
+  // the circle offsets once per iteration (each part rounded once, as for
+  // the FP64 difference).  FULL: every circle slot is used (m = C), the
+  // circle loop has no per-circle test.
   T Sx[C], Sy[C];
-  auto project_obstacle = [&](T ux, T uy, const Pair<T> o, const Quad<T> p) {
-    const T dxj = off_x(o.x), dyj = off_y(o.y);
+  T xh = T(0), yh = T(0), rxl[C], ryl[C];
+  auto project_obstacle = [&](auto full, const Pair<T> o, const Quad<T> p) {
+    constexpr bool FULL = decltype(full)::value;
+    const T dxj = xh - o.x, dyj = yh - o.y;
 #pragma unroll
     for (int i = 0; i < C; ++i) {
-      if (i < m) {
-        const T xt = dxj + rr[i] * ux, yt = dyj + rr[i] * uy;
+      if (FULL || i < m) {
+        const T xt = dxj + rxl[i], yt = dyj + ryl[i];
         const T r2 = p.b * xt * xt + p.a * yt * yt;   // b^2 x~^2 + a^2 y~^2
         const T f1 = fmax(T(0), p.c * Num<T>::rsqrt_fast(r2) - T(1));
         Sx[i] += xt * f1;
         Sy[i] += yt * f1;
       }
+    }
+  };
+  // The near obstacles of the mask, each one's LDS data loaded while the
+  // previous one is projected (two register sets in turn).
+  auto project_near = [&](auto full, uint64_t mask) {
+    int j = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    Pair<T> o0 = oxy[j * q + tt], o1;
+    Quad<T> p0 = opq[j * 2], p1;
+    while (true) {
+      bool more = mask != 0;
+      j = more ? __builtin_ctzll(mask) : j;
+      mask &= mask - 1;
+      o1 = oxy[j * q + tt];
+      p1 = opq[j * 2];
+      project_obstacle(full, o0, p0);
+      if (!more) break;
+      more = mask != 0;
+      j = more ? __builtin_ctzll(mask) : j;
+      mask &= mask - 1;
+      o0 = oxy[j * q + tt];
+      p0 = opq[j * 2];
+      project_obstacle(full, o1, p1);
+      if (!more) break;
     }
   };
 
@@ -413,7 +446,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const T ux = slack ? cc : cps, uy = slack ? ss : sps;
 #pragma unroll
     for (int i = 0; i < C; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
-    const T x = T(xa), y = T(ya);   // for the vote only
+    const T x = T(xa), y = T(ya);   // for the vote and the projection
     if (!literal_alpha) {
       // Wave-wide vote: obstacles within ext + max(a, b) + margin of some
       // lane's robot centre, ext = max|r_i| |u| the reach of its circles.
@@ -454,25 +487,18 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
           }
         }
       }
-      // active obstacles, the next one's data loaded while this one is used
-      uint64_t near_mask = near_set;
-      if (near_mask) {
-        int j = __builtin_ctzll(near_mask);
-        near_mask &= near_mask - 1;
-        Pair<T> o = oxy[j * q + tt];
-        Quad<T> p = opq[j * 2];
-        while (true) {
-          const bool more = near_mask != 0;
-          const int jn = more ? __builtin_ctzll(near_mask) : j;
-          near_mask &= near_mask - 1;
-          const Pair<T> on = oxy[jn * q + tt];
-          const Quad<T> pn = opq[jn * 2];
-          project_obstacle(ux, uy, o, p);
-          if (!more) break;
-          j = jn;
-          o = on;
-          p = pn;
+      // active obstacles
+      if (near_set) {
+        xh = x;
+        yh = y;
+        const T xl = T(xa - double(xh)), yl = T(ya - double(yh));
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+          rxl[i] = xl + rr[i] * ux;
+          ryl[i] = yl + rr[i] * uy;
         }
+        if (m == C) project_near(std::true_type(), near_set);
+        else project_near(std::false_type(), near_set);
       }
     } else {
       for (int j = 0; j < n; ++j) {
