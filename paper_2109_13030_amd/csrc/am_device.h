@@ -146,27 +146,33 @@ struct FusedLds {
 
 // Per-wave vectors.  Position-block vectors hold one axis in 2nv contiguous
 // entries (x block then slack block), padded to a2 = pad4(2nv).  The
-// coefficients are kept in FP64 (zd; dw elements of T per double) with a T
-// copy (z) for the derivative channels; w and dz are the T operands of the
-// coefficient update's two products; wd stages the FP64 multipliers for
-// the write-back.
+// coefficients are kept in FP64 (zd; dw elements of T per double); w and dz
+// are the T operands of the coefficient update's two products; wd stages
+// the FP64 multipliers for the write-back.  dz (its four blocks pad4(nv)
+// apart) and the heading coefficients zpsi are read by every lane against
+// its basis rows, which a lane holds in its own order (slot 4i + k holds
+// row 4i + (k ^ (lane & 3))); both are stored in four copies, copy s in
+// that order for the lanes with lane & 3 = s (copy 0 is the natural
+// order).  The copy strides put the four copies' 16-byte groups in
+// different LDS banks.
 struct WaveLds {
-  int z, w, dz, zd, wd, zpsi, aux, red;
+  int w, dz, zd, wd, zpsi, aux, red;
 };
 
 __host__ __device__ constexpr int pad8(int v) { return (v + 7) & ~7; }
+__host__ __device__ constexpr int dz_copy_stride(int nv) { return 2 * pad4(2 * nv) + 4; }
+__host__ __device__ constexpr int zpsi_copy_stride(int nv) { return pad4(nv); }
 
 __host__ __device__ inline WaveLds wave_layout(int nv, int red_rows, int dw) {
   const int p = pad4(nv), a2 = pad4(2 * nv);
   WaveLds w;
   int o = 0;
-  w.z = o; o += pad8(2 * a2);           // T copy of z of (x, c) and (y, s)
-  w.w = o; o += pad8(2 * a2);           // lambda - rho F^T (F xi - g)
-  w.dz = o; o += pad8(2 * a2);          // the last update of z
-  w.zd = o; o += pad8(2 * a2 * dw);     // z in FP64
-  w.wd = o; o += pad8(2 * a2 * dw);     // multipliers in FP64 (write-back)
-  w.zpsi = o; o += pad8(p);             // heading coefficients
-  w.aux = o; o += pad8(2 * a2 + p);     // set-up staging
+  w.w = o; o += pad8(2 * a2);                      // lambda - rho F^T (F xi - g)
+  w.dz = o; o += pad8(4 * dz_copy_stride(nv));     // the last update of z (4 copies)
+  w.zd = o; o += pad8(2 * a2 * dw);                // z in FP64
+  w.wd = o; o += pad8(2 * a2 * dw);                // multipliers in FP64 (write-back)
+  w.zpsi = o; o += pad8(4 * zpsi_copy_stride(nv)); // heading coefficients (4 copies)
+  w.aux = o; o += pad8(2 * a2 + p);                // set-up staging
   w.red = o; o += red_rows * kRedRowStride;
   return w;
 }

@@ -103,50 +103,52 @@ __device__ __forceinline__ double lane_xor2(double v) {
   return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
 }
 
-// Sums over the 64 lanes of G per-lane partials.  Two DPP levels first:
-// lane pairs add (odd lanes keeping the odd row of each register pair), then
-// quads exchange (lanes with bit 1 set keeping the second pair-register), so
-// lane L holds row 4i + L % 4 of quad register i summed over its quad; the
-// 16 quad sums of a row go to LDS and lane g adds row g with four
-// interleaved accumulators.  Rows go through LDS in passes of ROWS (a
-// multiple of 4).  On return lane g (g < G) holds the total of partial g;
-// the passes do not change the order of any addition.  (A plain add takes
-// the neighbour through its DPP operand, one instruction; fused into the
+// Total of the 16 quad sums of one reduction row, with four interleaved
+// accumulators.
+template <typename T>
+__device__ __forceinline__ T quad_row_total(const T *row_base) {
+#pragma clang fp contract(off)
+  const Quad<T> *row = reinterpret_cast<const Quad<T> *>(row_base);
+  const Quad<T> v0 = row[0];
+  T s0 = v0.a, s1 = v0.b, s2 = v0.c, s3 = v0.d;
+#pragma unroll
+  for (int c = 1; c < 4; ++c) {
+    const Quad<T> v = row[c];
+    s0 += v.a; s1 += v.b; s2 += v.c; s3 += v.d;
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
+// Sums over the 64 lanes of G per-lane partials (G a multiple of 4) that
+// come in lane-permuted slots: on lane L, slot 4i + k holds the partial of
+// row 4i + (k ^ (L % 4)).  Slot 4i + 1 of the neighbour L ^ 1 holds the row
+// of slot 4i here, so one DPP add per row pair gives this row's sum over the
+// lane pair; likewise slots 4i + 2 and 4i + 3 give the sum of the row that
+// lane L ^ 2 holds, and one more DPP add across the quad leaves lane L with
+// row 4i + L % 4 summed over its quad, with no selects.  The 16 quad sums
+// of a row go to LDS and lane g adds row g with four interleaved
+// accumulators.  Rows go through LDS in passes of ROWS (a multiple of 4).
+// On return lane g (g < G) holds the total of row g; the order of the
+// additions does not depend on the pass size.  (A plain add takes the
+// neighbour through its DPP operand, one instruction; fused into the
 // caller's product it would need a separate DPP move and the product twice.)
 template <typename T, int G, int ROWS>
-__device__ __forceinline__ T wave_sum_quad(const T (&p)[G], T *red, int lane) {
+__device__ __forceinline__ T wave_sum_perm(const T (&p)[G], T *red, int lane) {
 #pragma clang fp contract(off)
-  constexpr int G1 = (G + 1) / 2, G2 = (G1 + 1) / 2, RPP = ROWS / 4;   // quad registers per pass
-  static_assert(ROWS <= kRedRows && ROWS % 4 == 0, "rows per pass");
-  const bool odd = lane & 1, hi2 = lane & 2;
-  T r1[G1];
-#pragma unroll
-  for (int j = 0; j < G1; ++j) {
-    const T a = p[2 * j] + lane_xor1(p[2 * j]);
-    const T b = 2 * j + 1 < G ? p[2 * j + 1] + lane_xor1(p[2 * j + 1]) : T(0);
-    r1[j] = odd ? b : a;
-  }
+  constexpr int NQ = G / 4, RPP = ROWS / 4;   // row groups, per pass
+  static_assert(G % 4 == 0 && ROWS <= kRedRows && ROWS % 4 == 0, "row groups");
   T s = T(0);
 #pragma unroll
-  for (int i0 = 0; i0 < G2; i0 += RPP) {
+  for (int i0 = 0; i0 < NQ; i0 += RPP) {
 #pragma unroll
-    for (int i = i0; i < G2 && i < i0 + RPP; ++i) {
-      const T c = r1[2 * i] + lane_xor2(r1[2 * i]);
-      const T d = 2 * i + 1 < G1 ? r1[2 * i + 1] + lane_xor2(r1[2 * i + 1]) : T(0);
-      red[(4 * (i - i0) + (lane & 3)) * kRedRowStride + (lane >> 2)] = hi2 ? d : c;
+    for (int i = i0; i < NQ && i < i0 + RPP; ++i) {
+      const T a = p[4 * i] + lane_xor1(p[4 * i + 1]);
+      const T b = p[4 * i + 2] + lane_xor1(p[4 * i + 3]);
+      red[(4 * (i - i0) + (lane & 3)) * kRedRowStride + (lane >> 2)] = a + lane_xor2(b);
     }
     wave_sync();
     const int g0 = 4 * i0;
-    if (lane >= g0 && lane < G && lane < g0 + ROWS) {
-      const Quad<T> *row = reinterpret_cast<const Quad<T> *>(red + (lane - g0) * kRedRowStride);
-      T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const Quad<T> v = row[c];
-        s0 += v.a; s1 += v.b; s2 += v.c; s3 += v.d;
-      }
-      s = (s0 + s1) + (s2 + s3);
-    }
+    if (lane >= g0 && lane < G && lane < g0 + ROWS) s = quad_row_total(red + (lane - g0) * kRedRowStride);
     wave_sync();
   }
   return s;
@@ -175,7 +177,8 @@ template <typename T, int NV, int C, int RED>
 __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds, const FusedLds &L,
                            int lane, int wave) {
   constexpr int A2 = pad4(2 * NV), N2 = 2 * NV;
-  constexpr int G = 4 * NV;   // rows of the per-iteration reduction
+  constexpr int NP = pad4(NV);   // basis rows padded to whole 4-row groups
+  constexpr int G = 4 * NP;      // rows of the per-iteration reduction (4 blocks of NP)
   constexpr int DW = int(sizeof(double) / sizeof(T));   // elements of T per FP64 value
   // descriptor fields used in the loop, as locals
   const int q = uni(Dsrc.q), m = uni(Dsrc.m), n = uni(Dsrc.n), flags = uni(Dsrc.flags), K = uni(Dsrc.K);
@@ -199,13 +202,24 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   const Pair<T> *oxy = reinterpret_cast<const Pair<T> *>(lds + L.oxy);
   const T *op = lds + L.op;
   const Quad<T> *opq = reinterpret_cast<const Quad<T> *>(lds + L.op);
-  constexpr int QS = pad4(NV);   // row stride of the Q rows and block stride of dz
+  constexpr int QS = NP;   // row stride of the Q rows and block stride of dz
   static_assert(QS + NV <= A2, "both blocks of dz fit one axis's area");
+  // this lane's slot order: slot 4i + k holds row 4i + (k ^ sq)
+  const int sq = lane & 3;
+  constexpr int DZC = dz_copy_stride(NV), ZPC = zpsi_copy_stride(NV);
   const T *M1 = lds + L.m1, *QL = lds + L.qrows;
   const WaveLds wl = wave_layout(NV, RED, DW);
   T *wb = lds + L.wave0 + wave * L.wave_stride;
-  T *vz = wb + wl.z, *vzpsi = wb + wl.zpsi, *vaux = wb + wl.aux;
-  T *vw = wb + wl.w, *vdz = wb + wl.dz;
+  T *vzpsi = wb + wl.zpsi, *vaux = wb + wl.aux;   // vzpsi: copy 0 (natural order)
+  T *vw = wb + wl.w, *vdz = wb + wl.dz;            // vdz: copy 0 (natural order)
+  const Quad<T> *dzq = reinterpret_cast<const Quad<T> *>(vdz + sq * DZC);      // this lane's copies
+  const Quad<T> *zpsiq = reinterpret_cast<const Quad<T> *>(vzpsi + sq * ZPC);
+  // element r of a vector held in the four lane-permuted copies
+  auto put4 = [](T *v, int stride, int r, T x) {
+    const int g = r & ~3, k = r & 3;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c * stride + g + (k ^ c)] = x;
+  };
   double *vzd = reinterpret_cast<double *>(wb + wl.zd), *vwd = reinterpret_cast<double *>(wb + wl.wd);
   T *red = wb + wl.red;
   // exchange area of this trajectory: [half][kXchHalf]
@@ -228,13 +242,17 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   const T *gU = static_cast<const T *>(Dsrc.U), *gV = static_cast<const T *>(Dsrc.V),
           *gW = static_cast<const T *>(Dsrc.W), *gUt = static_cast<const T *>(Dsrc.Ut),
           *gM2 = static_cast<const T *>(Dsrc.M2);
-  T Ub[NV], Vb[NV], Wb[NV], Ut[NV];
+  // (in this lane's slot order; rows past nv are zero)
+  T Ub[NP], Vb[NP], Wb[NP], Ut[NP];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    Ub[k] = tv ? gU[tt * NV + k] : T(0);
-    Vb[k] = tv ? gV[tt * NV + k] : T(0);
-    Wb[k] = tv ? gW[tt * NV + k] : T(0);
-    Ut[k] = tv ? gUt[tt * NV + k] : T(0);
+  for (int k = 0; k < NP; ++k) {
+    const int r = (k & ~3) | ((k & 3) ^ sq);
+    const bool use = tv && r < NV;
+    const int e = use ? tt * NV + r : 0;
+    Ub[k] = use ? gU[e] : T(0);
+    Vb[k] = use ? gV[e] : T(0);
+    Wb[k] = use ? gW[e] : T(0);
+    Ut[k] = use ? gUt[e] : T(0);
   }
 
   // ---- boundary terms h = H b (centred positions) and the initial state
@@ -260,7 +278,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     }
     zl = zz;
     vzd[axis * A2 + I] = zz;
-    vz[axis * A2 + I] = T(zz);
+    // (z itself goes through the dz copies for the first evaluation)
+    put4(vdz, DZC, axis * A2 + (I / NV) * QS + I % NV, T(zz));
     // lambda_z = R^-T lambda
     const T *glam = static_cast<const T *>(Dsrc.lam);
     double lz = 0.0;
@@ -285,7 +304,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       const double t = R[kk * NV + j] * double(src[size_t(l) * NV + j]);
       zz += j >= kk ? t : 0.0;
     }
-    vzpsi[kk] = T(zz);
+    put4(vzpsi, ZPC, kk, T(zz));
     const T *glp = static_cast<const T *>(Dsrc.lampsi);
     double lz = 0.0;
 #pragma unroll
@@ -336,27 +355,27 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   T xd, xdd, cc, yd, ydd, ss, psi, cps, sps, psih;
   T racc = T(0);   // sum over the iterations of psi_sign (psi - psi_hat) at t
 
-  // derivative and slack channels from the initial z (first call), then
-  // every channel advanced by the product of the update dz (its blocks QS
-  // apart in LDS), the positions in FP64
+  // derivative and slack channels from the initial z (first call: z in the
+  // dz copies), then every channel advanced by the product of the update dz
+  // (its blocks QS apart in LDS, read in this lane's slot order), the
+  // positions in FP64
   auto eval_xy = [&](bool step) {
     T a0 = 0, b0 = 0, a1 = 0, a2 = 0, a3 = 0, b1 = 0, b2 = 0, b3 = 0;
-    if (!step) {
 #pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        const T zx = vz[k], zc = vz[NV + k], zy = vz[A2 + k], zs = vz[A2 + NV + k];
-        a1 += Vb[k] * zx; a2 += Wb[k] * zx; a3 += Ub[k] * zc;
-        b1 += Vb[k] * zy; b2 += Wb[k] * zy; b3 += Ub[k] * zs;
+    for (int c = 0; c < NP / 4; ++c) {
+      const Quad<T> dx = dzq[c], dc = dzq[QS / 4 + c], dy = dzq[A2 / 4 + c], ds = dzq[(A2 + QS) / 4 + c];
+      const T *vx = &dx.a, *vc = &dc.a, *vy = &dy.a, *vs = &ds.a;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 4 * c + e;
+        a0 += Ub[k] * vx[e]; a1 += Vb[k] * vx[e]; a2 += Wb[k] * vx[e]; a3 += Ub[k] * vc[e];
+        b0 += Ub[k] * vy[e]; b1 += Vb[k] * vy[e]; b2 += Wb[k] * vy[e]; b3 += Ub[k] * vs[e];
       }
+    }
+    if (!step) {
       xd = a1; xdd = a2; cc = a3;
       yd = b1; ydd = b2; ss = b3;
       return;
-    }
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      const T dx = vdz[k], dc = vdz[QS + k], dy = vdz[A2 + k], ds = vdz[A2 + QS + k];
-      a0 += Ub[k] * dx; a1 += Vb[k] * dx; a2 += Wb[k] * dx; a3 += Ub[k] * dc;
-      b0 += Ub[k] * dy; b1 += Vb[k] * dy; b2 += Wb[k] * dy; b3 += Ub[k] * ds;
     }
     xa += double(a0);
     ya += double(b0);
@@ -370,7 +389,13 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   auto eval_psi = [&]() {
     T p = 0;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) p += Ub[k] * vzpsi[k];
+    for (int c = 0; c < NP / 4; ++c) {
+      const Quad<T> z = zpsiq[c];
+      p += Ub[4 * c] * z.a;
+      p += Ub[4 * c + 1] * z.b;
+      p += Ub[4 * c + 2] * z.c;
+      p += Ub[4 * c + 3] * z.d;
+    }
     psi = p;
     T sn, cs;
     Num<T>::sincos_(p, &sn, &cs);
@@ -575,32 +600,33 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     // [V W U] on the position block and U on the slack block)
     // (the velocity and acceleration rows are usually inside their discs on
     // every lane of the wave; their terms are then zero and are left out)
+    // (blocks of NP rows, in this lane's slot order)
     T pr[G];
     if (__ballot((fv > T(0)) | (fa > T(0))) != 0) {
 #pragma unroll
-      for (int k = 0; k < NV; ++k) {
+      for (int k = 0; k < NP; ++k) {
         pr[k] = Vb[k] * rvx + Wb[k] * rax + Ub[k] * ro1x;
-        pr[2 * NV + k] = Vb[k] * rvy + Wb[k] * ray + Ub[k] * ro1y;
+        pr[2 * NP + k] = Vb[k] * rvy + Wb[k] * ray + Ub[k] * ro1y;
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < NV; ++k) {
+      for (int k = 0; k < NP; ++k) {
         pr[k] = Ub[k] * ro1x;
-        pr[2 * NV + k] = Ub[k] * ro1y;
+        pr[2 * NP + k] = Ub[k] * ro1y;
       }
     }
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      pr[NV + k] = Ub[k] * ro2x;
-      pr[3 * NV + k] = Ub[k] * ro2y;
+    for (int k = 0; k < NP; ++k) {
+      pr[NP + k] = Ub[k] * ro2x;
+      pr[3 * NP + k] = Ub[k] * ro2y;
     }
     // the reduction and exchange are the pair's critical path: while a wave
     // is in them the SIMD issues its instructions first
     __builtin_amdgcn_s_setprio(2);
-    const T tot = wave_sum_quad<T, G, RED>(pr, red, lane);
+    const T tot = wave_sum_perm<T, G, RED>(pr, red, lane);
     if (lane < G) xmine[lane] = tot;
     __syncthreads();
-    if (prow) tr = exchange_sum(lane);
+    if (prow) tr = exchange_sum((lane / NV) * NP + lane % NV);
     __builtin_amdgcn_s_setprio(0);
   };
 
@@ -682,7 +708,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     const double dz = double(m1_dot(vw + axis * A2)) - bcc;
     bcc = 0.0;
     zl += dz;
-    if (prow) vdz[axis * A2 + qb * QS + qi] = T(dz);
+    if (prow) put4(vdz, DZC, axis * A2 + qb * QS + qi, T(dz));
     wave_sync();
     eval_xy(true);
 
@@ -700,16 +726,16 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       psih_prev = pnew;
       psih = pnew;
     }
-    T pp[NV];
+    T pp[NP];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) pp[k] = Ut[k] * dpsi;
+    for (int k = 0; k < NP; ++k) pp[k] = Ut[k] * dpsi;
     __builtin_amdgcn_s_setprio(2);
-    const T upsi = wave_sum_quad<T, NV, RED>(pp, red, lane);
+    const T upsi = wave_sum_perm<T, NP, RED>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = upsi;
     __syncthreads();
     if (hrow) {
       zpsi_d += double(exchange_sum(kXchBig + lane));
-      vzpsi[lane] = T(zpsi_d);
+      put4(vzpsi, ZPC, lane, T(zpsi_d));
     }
     __builtin_amdgcn_s_setprio(0);
     wave_sync();
@@ -729,10 +755,10 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 
   // ---- lambda_psi = lambda_psi(0) - rho_psi U^T (sum of psi - psi_hat)
   {
-    T pp[NV];
+    T pp[NP];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) pp[k] = Ub[k] * racc;
-    const T s = wave_sum_quad<T, NV, RED>(pp, red, lane);
+    for (int k = 0; k < NP; ++k) pp[k] = Ub[k] * racc;
+    const T s = wave_sum_perm<T, NP, RED>(pp, red, lane);
     if (lane < NV) xmine[kXchBig + lane] = s;
     __syncthreads();
     if (hrow) vaux[2 * A2 + lane] = lampsi0 - rhop * exchange_sum(kXchBig + lane);
@@ -787,9 +813,14 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       }
       T psd = T(0), psdd = T(0);
 #pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        psd += Vb[k] * vzpsi[k];
-        psdd += Wb[k] * vzpsi[k];
+      for (int c = 0; c < NP / 4; ++c) {
+        const Quad<T> z = zpsiq[c];
+        const T *zv = &z.a;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          psd += Vb[4 * c + e] * zv[e];
+          psdd += Wb[4 * c + e] * zv[e];
+        }
       }
       v2 = xd * xd + yd * yd;
       a2 = xdd * xdd + ydd * ydd;
