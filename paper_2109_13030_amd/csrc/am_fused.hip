@@ -415,11 +415,12 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // per-obstacle difference is one FP32 subtraction and the remainder joins
   // the circle offsets once per iteration (each part rounded once, as for
   // the FP64 difference).  FULL: every circle slot is used (m = C), the
-  // circle loop has no per-circle test.
+  // circle loop has no per-circle test.  FIRST: the first obstacle, whose
+  // terms start the sums.
   T Sx[C], Sy[C];
   T xh = T(0), yh = T(0), rxl[C], ryl[C];
-  auto project_obstacle = [&](auto full, const Pair<T> o, const Quad<T> p) {
-    constexpr bool FULL = decltype(full)::value;
+  auto project_obstacle = [&](auto full, auto first, const Pair<T> o, const Quad<T> p) {
+    constexpr bool FULL = decltype(full)::value, FIRST = decltype(first)::value;
     const T dxj = xh - o.x, dyj = yh - o.y;
 #pragma unroll
     for (int i = 0; i < C; ++i) {
@@ -427,40 +428,55 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
         const T xt = dxj + rxl[i], yt = dyj + ryl[i];
         const T r2 = p.b * xt * xt + p.a * yt * yt;   // b^2 x~^2 + a^2 y~^2
         const T f1 = fmax(T(0), p.c * Num<T>::rsqrt_fast(r2) - T(1));
-        Sx[i] += xt * f1;
-        Sy[i] += yt * f1;
+        if constexpr (FIRST) {
+          Sx[i] = xt * f1;
+          Sy[i] = yt * f1;
+        } else {
+          Sx[i] += xt * f1;
+          Sy[i] += yt * f1;
+        }
+      } else if constexpr (FIRST) {
+        Sx[i] = T(0);
+        Sy[i] = T(0);
       }
     }
   };
-  // The near obstacles of the mask, each one's LDS data loaded while the
-  // previous one is projected (two register sets in turn).
+  // The near obstacles of the (non-empty) mask, each one's LDS data loaded
+  // while the previous one is projected (two register sets in turn).
   auto project_near = [&](auto full, uint64_t mask) {
     int j = __builtin_ctzll(mask);
     mask &= mask - 1;
     Pair<T> o0 = oxy[j * q + tt], o1;
     Quad<T> p0 = opq[j * 2], p1;
+    bool more = mask != 0;
+    j = more ? __builtin_ctzll(mask) : j;
+    mask &= mask - 1;
+    o1 = oxy[j * q + tt];
+    p1 = opq[j * 2];
+    project_obstacle(full, std::true_type(), o0, p0);
+    if (!more) return;
     while (true) {
-      bool more = mask != 0;
-      j = more ? __builtin_ctzll(mask) : j;
-      mask &= mask - 1;
-      o1 = oxy[j * q + tt];
-      p1 = opq[j * 2];
-      project_obstacle(full, o0, p0);
-      if (!more) break;
       more = mask != 0;
       j = more ? __builtin_ctzll(mask) : j;
       mask &= mask - 1;
       o0 = oxy[j * q + tt];
       p0 = opq[j * 2];
-      project_obstacle(full, o1, p1);
+      project_obstacle(full, std::false_type(), o1, p1);
+      if (!more) break;
+      more = mask != 0;
+      j = more ? __builtin_ctzll(mask) : j;
+      mask &= mask - 1;
+      o1 = oxy[j * q + tt];
+      p1 = opq[j * 2];
+      project_obstacle(full, std::false_type(), o0, p0);
       if (!more) break;
     }
   };
 
   // ---- xi3/xi4 projection of every (circle, obstacle, t), velocity and
-  // acceleration, then the per-wave partial sums of F^T (F xi - g) (rows
-  // 0..4nv-1), exchanged between the two waves; afterwards lane k < 4nv
-  // holds row k of the total in `tr`.  `rp` keeps this lane's heading
+  // acceleration, then the per-wave partial sums of F^T (F xi - g) (4
+  // blocks of NP rows), exchanged between the two waves; afterwards lane
+  // (axis, I) of the position rows holds its row of the total in `tr`.  `rp` keeps this lane's heading
   // residual psi_sign (psi - psi_hat) for the next heading step.
   T tr = T(0), rp = T(0);
   // near-obstacle set of the last vote and the positions it was taken at
@@ -469,8 +485,6 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   bool voted = false;
   auto project_reduce = [&](bool with_psi) {
     const T ux = slack ? cc : cps, uy = slack ? ss : sps;
-#pragma unroll
-    for (int i = 0; i < C; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
     const T x = T(xa), y = T(ya);   // for the vote and the projection
     if (!literal_alpha) {
       // Wave-wide vote: obstacles within ext + max(a, b) + margin of some
@@ -524,8 +538,13 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
         }
         if (m == C) project_near(std::true_type(), near_set);
         else project_near(std::false_type(), near_set);
+      } else {
+#pragma unroll
+        for (int i = 0; i < C; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
       }
     } else {
+#pragma unroll
+      for (int i = 0; i < C; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
       for (int j = 0; j < n; ++j) {
         const Pair<T> o = oxy[j * q + tt];
         const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
@@ -544,9 +563,10 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     }
     T Dx = 0, Dy = 0, DRx = 0, DRy = 0;
     auto sum_circles = [&]() {
-      Dx = Dy = DRx = DRy = T(0);
+      Dx = Sx[0]; Dy = Sy[0];
+      DRx = rr[0] * Sx[0]; DRy = rr[0] * Sy[0];
 #pragma unroll
-      for (int i = 0; i < C; ++i) {
+      for (int i = 1; i < C; ++i) {
         Dx += Sx[i]; Dy += Sy[i];
         DRx += rr[i] * Sx[i]; DRy += rr[i] * Sy[i];
       }
