@@ -414,17 +414,19 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // position split into its FP32 rounding xh and the remainder xl, so the
   // per-obstacle difference is one FP32 subtraction and the remainder joins
   // the circle offsets once per iteration (each part rounded once, as for
-  // the FP64 difference).  FULL: every circle slot is used (m = C), the
-  // circle loop has no per-circle test.  FIRST: the first obstacle, whose
-  // terms start the sums.
+  // the FP64 difference).  MC > 0: exactly the first MC circle slots are
+  // used (MC = m, a compile-time count), so the circle loop has no
+  // per-circle test; MC = 0 tests every slot against m.  FIRST: the first
+  // obstacle, whose terms start the sums.
   T Sx[C], Sy[C];
   T xh = T(0), yh = T(0), rxl[C], ryl[C];
-  auto project_obstacle = [&](auto full, auto first, const Pair<T> o, const Quad<T> p) {
-    constexpr bool FULL = decltype(full)::value, FIRST = decltype(first)::value;
+  auto project_obstacle = [&](auto count, auto first, const Pair<T> o, const Quad<T> p) {
+    constexpr int MC = decltype(count)::value;
+    constexpr bool FIRST = decltype(first)::value;
     const T dxj = xh - o.x, dyj = yh - o.y;
 #pragma unroll
     for (int i = 0; i < C; ++i) {
-      if (FULL || i < m) {
+      if (MC > 0 ? i < MC : i < m) {
         const T xt = dxj + rxl[i], yt = dyj + ryl[i];
         const T r2 = p.b * xt * xt + p.a * yt * yt;   // b^2 x~^2 + a^2 y~^2
         const T f1 = fmax(T(0), p.c * Num<T>::rsqrt_fast(r2) - T(1));
@@ -443,7 +445,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   };
   // The near obstacles of the (non-empty) mask, each one's LDS data loaded
   // while the previous one is projected (two register sets in turn).
-  auto project_near = [&](auto full, uint64_t mask) {
+  auto project_near = [&](auto count, uint64_t mask) {
     int j = __builtin_ctzll(mask);
     mask &= mask - 1;
     Pair<T> o0 = oxy[j * q + tt], o1;
@@ -453,7 +455,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     mask &= mask - 1;
     o1 = oxy[j * q + tt];
     p1 = opq[j * 2];
-    project_obstacle(full, std::true_type(), o0, p0);
+    project_obstacle(count, std::true_type(), o0, p0);
     if (!more) return;
     while (true) {
       more = mask != 0;
@@ -461,14 +463,14 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
       mask &= mask - 1;
       o0 = oxy[j * q + tt];
       p0 = opq[j * 2];
-      project_obstacle(full, std::false_type(), o1, p1);
+      project_obstacle(count, std::false_type(), o1, p1);
       if (!more) break;
       more = mask != 0;
       j = more ? __builtin_ctzll(mask) : j;
       mask &= mask - 1;
       o1 = oxy[j * q + tt];
       p1 = opq[j * 2];
-      project_obstacle(full, std::false_type(), o0, p0);
+      project_obstacle(count, std::false_type(), o0, p0);
       if (!more) break;
     }
   };
@@ -536,8 +538,12 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
           rxl[i] = xl + rr[i] * ux;
           ryl[i] = yl + rr[i] * uy;
         }
-        if (m == C) project_near(std::true_type(), near_set);
-        else project_near(std::false_type(), near_set);
+        // exact circle counts for m = C, C - 1 and C - 2 (every robot and
+        // uneven batch here), the tested form otherwise
+        if (m == C) project_near(std::integral_constant<int, C>(), near_set);
+        else if (C > 1 && m == C - 1) project_near(std::integral_constant<int, (C > 1 ? C - 1 : 0)>(), near_set);
+        else if (C > 2 && m == C - 2) project_near(std::integral_constant<int, (C > 2 ? C - 2 : 0)>(), near_set);
+        else project_near(std::integral_constant<int, 0>(), near_set);
       } else {
 #pragma unroll
         for (int i = 0; i < C; ++i) { Sx[i] = T(0); Sy[i] = T(0); }
