@@ -196,10 +196,12 @@ def test_c1_f32_matches_oracle():
     _fp32_gate(pb, init, 50)
 
 
-@pytest.mark.parametrize("m", [1, 6, 8])
+@pytest.mark.parametrize("m", [1, 2, 4, 6, 7, 8])
 def test_f32_circle_counts_against_oracle(m):
-    """FP32 with 1, 6 and 8 circles: the kernel instance with room for five
-    circles (m <= 5) and the one with room for eight."""
+    """FP32 with 1 to 8 circles: the kernel instance with room for five
+    circles (m <= 5) and the one with room for eight, each through its
+    projection loops for m = C, C - 1, C - 2 and the general one (m = 3 and
+    5 are c1 and c2)."""
     import dataclasses
     cfg = dataclasses.replace(inputs.CONFIGS["c2"], circles=m)
     pb = inputs.make_problem(cfg, 21)
