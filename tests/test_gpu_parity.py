@@ -95,6 +95,35 @@ def test_c1_f64_matches_oracle():
     _compare_f64(pb, init, 50)
 
 
+# (v_max, a_max, least clamped share of (trajectory, t) for d_v and d_a
+# after 30 iterations): bounds below what the start-goal distance needs
+# (~0.38 m/s on average), clamping at most time steps from the start; and
+# bounds that no time step reaches in the first iterations and about a third
+# reach by the end, so the discs become active during the solve
+_DISCS = [(0.25, 0.002, 0.5, 0.5), (0.7, 0.15, 0.2, 0.3)]
+
+
+@pytest.mark.parametrize("plain", [False, True])
+@pytest.mark.parametrize("vmax,amax,share_v,share_a", _DISCS)
+def test_active_velocity_and_acceleration_discs_f64(vmax, amax, share_v, share_a, plain):
+    """The disc projections of eqs. compute_dv and compute_da clamp (d_v =
+    d_a = 1 at the clamped time steps): fused and plain FP64 paths against
+    the oracle."""
+    pb, init = inputs.workload("c1", batch=8)
+    pb = dict(pb, vmax=vmax, amax=amax)
+    _, ost = _compare_f64(pb, init, 30, plain=plain)
+    assert (ost["dv"] >= 1.0 - 1e-12).mean() > share_v
+    assert (ost["da"] >= 1.0 - 1e-12).mean() > share_a
+
+
+@pytest.mark.parametrize("vmax,amax,share_v,share_a", _DISCS)
+def test_active_velocity_and_acceleration_discs_f32(vmax, amax, share_v, share_a):
+    """The same clamped problems in FP32 against the oracle."""
+    pb, init = inputs.workload("c1", batch=8)
+    pb = dict(pb, vmax=vmax, amax=amax)
+    _fp32_gate(pb, init, 30)
+
+
 @pytest.mark.parametrize("flags", [oracle.ALPHA_LITERAL, oracle.XTILDE_SLACK, oracle.PSI_NO_UNWRAP,
                                    oracle.Q_CS_ZERO, oracle.LAMPSI_LITERAL])
 def test_readings_f64_match_oracle(flags):
