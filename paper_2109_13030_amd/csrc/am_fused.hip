@@ -36,8 +36,10 @@
 //    the multipliers, Q z and the update itself are carried in FP64 (Q z' =
 //    Q z + Q dz with the product of the small update in T; Q is the
 //    block-diagonal smoothness term W^T W), and so are the positions (x' =
-//    x + U dz likewise) and their offsets from the obstacle centres.  A z = b
-//    holds after the first update, so the boundary term is applied once.
+//    x + U dz likewise); an offset from an obstacle centre is the FP32
+//    difference from the position's FP32 rounding plus the rounding
+//    remainder, each rounded once.  A z = b holds after the first update,
+//    so the boundary term is applied once.
 //  * The heading step (eq. compute_convex_surrogate) is z_psi = h_psi +
 //    M2 (lambda_psi + rho U^T psi_hat).  With mu = M2 lambda_psi and the rows
 //    of U~ = U M2^T, z_psi = h_psi + mu + rho U~^T psi_hat, and the
@@ -51,6 +53,10 @@
 //  * Coefficients are shifted by the midpoint of start and goal on entry and
 //    back on exit (exact: the basis reproduces constants, P 1 = 1,
 //    Pdot 1 = 0).
+//  * Each lane holds its rows of U, V, W and U~ in its own order (within
+//    groups of 4 rows, slot k holds row k xor (lane mod 4)), so the sums
+//    over t combine lanes without selects (wave_sum_perm); the vectors the
+//    lanes multiply against those rows are kept in LDS in the four orders.
 #include <hip/hip_runtime.h>
 
 #include <limits>
