@@ -195,6 +195,6 @@ __host__ __device__ inline FusedLds fused_layout(int q, int n, int nv, int tile,
 
 // Per-obstacle parameter slots in the op table (inflated semi-axes a, b):
 // the first four are read as one Quad in the projection loop.
-enum { OP_A2 = 0, OP_B2 = 1, OP_AB = 2, OP_AMAX = 3, OP_A = 4, OP_B = 5 };
+enum { OP_A2 = 0, OP_B2 = 1, OP_AB = 2, OP_AMAX = 3, OP_A = 4, OP_B = 5, OP_IA2 = 6, OP_IB2 = 7 };
 
 }  // namespace amk

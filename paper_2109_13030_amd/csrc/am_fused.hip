@@ -109,6 +109,44 @@ __device__ __forceinline__ double lane_xor2(double v) {
   return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
 }
 
+// DPP move with control CTRL on the rows of ROWS; lanes of the other rows
+// keep `id`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_rows(float v, float id) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, id), __builtin_bit_cast(int, v),
+                                                               CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows(double v, double id) {
+  const long long b = __builtin_bit_cast(long long, v), i = __builtin_bit_cast(long long, id);
+  const int lo = __builtin_amdgcn_update_dpp(int(i & 0xffffffffLL), int(b & 0xffffffffLL), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(int(i >> 32), int(b >> 32), CTRL, ROWS, 0xF, false);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ double lane63(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffLL), 63);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
+}
+
+// op over the 64 lanes (id its identity), the same on every lane: quads,
+// half rows and rows through lane permutations, then rows 0 + 1 and 2 + 3
+// through the row broadcasts of lanes 15 and 31, read from lane 63.
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_all(T v, T id, Op op) {
+  v = op(v, dpp_rows<0xB1, 0xF>(v, id));    // quad_perm [1, 0, 3, 2]
+  v = op(v, dpp_rows<0x4E, 0xF>(v, id));    // quad_perm [2, 3, 0, 1]
+  v = op(v, dpp_rows<0x141, 0xF>(v, id));   // row_half_mirror
+  v = op(v, dpp_rows<0x140, 0xF>(v, id));   // row_mirror
+  v = op(v, dpp_rows<0x142, 0xA>(v, id));   // row_bcast:15 into rows 1 and 3
+  v = op(v, dpp_rows<0x143, 0xC>(v, id));   // row_bcast:31 into rows 2 and 3
+  return lane63(v);
+}
+
 // Total of the 16 quad sums of one reduction row, with four interleaved
 // accumulators.
 template <typename T>
@@ -816,8 +854,11 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
         const Pair<T> o = oxy[j * q + t];
         const T a = op[j * 8 + OP_A], b = op[j * 8 + OP_B];
         const T aa = op[j * 8 + OP_A2], bb = op[j * 8 + OP_B2], ab = op[j * 8 + OP_AB];
+        const T iaa = op[j * 8 + OP_IA2], ibb = op[j * 8 + OP_IB2];
         const T dxj = off_x(o.x), dyj = off_y(o.y);
-        for (int i = 0; i < m; ++i) {
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+          if (i >= m) break;
           const T px = dxj + rr[i] * cps, py = dyj + rr[i] * sps;   // circle centre - obstacle
           const T xt = slack ? dxj + rr[i] * cc : px, yt = slack ? dyj + rr[i] * ss : py;
           T fx, fy;
@@ -840,7 +881,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
           const T f2 = fx * fx + fy * fy;
           fc2 = fmax(fc2, f2);
           fcsq += f2;
-          lvl2 = fmin(lvl2, px * px / aa + py * py / bb);
+          lvl2 = fmin(lvl2, px * px * iaa + py * py * ibb);
         }
       }
       T psd = T(0), psdd = T(0);
@@ -876,18 +917,9 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
     }
     if (prow) bad |= !isfinite(zl) || !isfinite(lam);
     if (hrow) bad |= !isfinite(vzpsi[lane]) || !isfinite(vaux[2 * A2 + lane]);
-    auto wmax = [](T v) {
-      for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-      return v;
-    };
-    auto wmin = [](T v) {
-      for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-      return v;
-    };
-    auto wadd = [](T v) {
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      return v;
-    };
+    auto wmax = [](T v) { return wave_all(v, T(0), [](T a, T b) { return fmax(a, b); }); };   // v >= 0
+    auto wmin = [](T v) { return wave_all(v, T(INFINITY), [](T a, T b) { return fmin(a, b); }); };
+    auto wadd = [](T v) { return wave_all(v, T(0), [](T a, T b) { return a + b; }); };
     T stv[NS] = {wmax(T(bad ? 1 : 0)), wmax(fc2), wadd(fcsq), wmin(lvl2), wmax(v2), wmax(a2), wmax(slk),
                  wmax(head), wmax(bc), wadd(cost)};
     if (lane == 0) {
@@ -1011,7 +1043,7 @@ __device__ __forceinline__ void fused_block(const Desc &D) {
     const T b = static_cast<const T *>(D.ob)[j] + rc;
     T *o = lds + L.op + j * 8;
     o[OP_A2] = a * a; o[OP_B2] = b * b; o[OP_AB] = a * b; o[OP_AMAX] = fmax(a, b);
-    o[OP_A] = a; o[OP_B] = b; o[6] = T(0); o[7] = T(0);
+    o[OP_A] = a; o[OP_B] = b; o[OP_IA2] = T(1) / (a * a); o[OP_IB2] = T(1) / (b * b);
   }
   const T *gM1 = static_cast<const T *>(D.M1);
   for (int e = tid; e < A2 * N2; e += blockDim.x) {
