@@ -109,44 +109,6 @@ __device__ __forceinline__ double lane_xor2(double v) {
   return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
 }
 
-// DPP move with control CTRL on the rows of ROWS; lanes of the other rows
-// keep `id`.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp_rows(float v, float id) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, id), __builtin_bit_cast(int, v),
-                                                               CTRL, ROWS, 0xF, false));
-}
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_rows(double v, double id) {
-  const long long b = __builtin_bit_cast(long long, v), i = __builtin_bit_cast(long long, id);
-  const int lo = __builtin_amdgcn_update_dpp(int(i & 0xffffffffLL), int(b & 0xffffffffLL), CTRL, ROWS, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(int(i >> 32), int(b >> 32), CTRL, ROWS, 0xF, false);
-  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
-}
-__device__ __forceinline__ float lane63(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
-}
-__device__ __forceinline__ double lane63(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffLL), 63);
-  const int hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
-  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | (static_cast<unsigned int>(lo)));
-}
-
-// op over the 64 lanes (id its identity), the same on every lane: quads,
-// half rows and rows through lane permutations, then rows 0 + 1 and 2 + 3
-// through the row broadcasts of lanes 15 and 31, read from lane 63.
-template <typename T, typename Op>
-__device__ __forceinline__ T wave_all(T v, T id, Op op) {
-  v = op(v, dpp_rows<0xB1, 0xF>(v, id));    // quad_perm [1, 0, 3, 2]
-  v = op(v, dpp_rows<0x4E, 0xF>(v, id));    // quad_perm [2, 3, 0, 1]
-  v = op(v, dpp_rows<0x141, 0xF>(v, id));   // row_half_mirror
-  v = op(v, dpp_rows<0x140, 0xF>(v, id));   // row_mirror
-  v = op(v, dpp_rows<0x142, 0xA>(v, id));   // row_bcast:15 into rows 1 and 3
-  v = op(v, dpp_rows<0x143, 0xC>(v, id));   // row_bcast:31 into rows 2 and 3
-  return lane63(v);
-}
-
 // Total of the 16 quad sums of one reduction row, with four interleaved
 // accumulators.
 template <typename T>

@@ -16,22 +16,16 @@ namespace amk {
 namespace {
 
 template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+__device__ __forceinline__ T wave_max(T v) {   // v >= 0
+  return wave_all(v, T(0), [](T a, T b) { return fmax(a, b); });
 }
 template <typename T>
 __device__ __forceinline__ T wave_min(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-  return v;
+  return wave_all(v, T(INFINITY), [](T a, T b) { return fmin(a, b); });
 }
 template <typename T>
 __device__ __forceinline__ T wave_add(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  return wave_all(v, T(0), [](T a, T b) { return a + b; });
 }
 
 struct ResArgs {
