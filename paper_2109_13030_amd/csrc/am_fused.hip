@@ -267,6 +267,22 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // boundary correction of the first update, in FP64
   double zl = 0.0, lam = 0.0, bcc = 0.0;
   T hpsi = T(0), lampsi0 = T(0);
+  // rows of the set-up operators this lane uses after the LDS exchanges
+  // below (H1, M2, the FP64 rows of U and Q), loaded first so that their
+  // latency overlaps that of the state loads
+  double h1r[6], udr[NV], qdr[NV];
+  T m2r[NV];
+  {
+    const int ih = prow ? I : 0, iu = tv ? tt : 0, iq = prow ? I % NV : 0, im = hrow ? lane : 0;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) h1r[e] = Dsrc.H1d[ih * 6 + e];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      udr[k] = Dsrc.Ud[iu * NV + k];
+      qdr[k] = Dsrc.Qd[iq * NV + k];
+      m2r[k] = gM2[im * NV + k];
+    }
+  }
   if (prow) {
     // z = R (c - off): the basis reproduces constants, so shifting all
     // coefficients of a position shifts its curve
@@ -332,14 +348,14 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
 #pragma unroll
       for (int k = 0; k < NV; ++k) ae += Dsrc.Abc[e * NV + k] * vzd[axis * A2 + k];
       const double be = (e == 0 || e == 3) ? bb[e] - off : bb[e];
-      bcc += Dsrc.H1d[I * 6 + e] * (ae - be);
+      bcc += h1r[e] * (ae - be);
     }
   }
   // mu = M2 lambda_psi (heading rows)
   T mu = T(0);
   if (hrow) {
 #pragma unroll
-    for (int j = 0; j < NV; ++j) mu += gM2[lane * NV + j] * vaux[j];
+    for (int j = 0; j < NV; ++j) mu += m2r[j] * vaux[j];
   }
   wave_sync();
 
@@ -351,7 +367,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   if (tv) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      const double u = Dsrc.Ud[tt * NV + k];
+      const double u = udr[k];
       xa += u * vzd[k];
       ya += u * vzd[A2 + k];
     }
@@ -723,7 +739,7 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   double qz = 0.0;
   if (prow && (qb == 0 || !(flags & AM_Q_CS_ZERO))) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) qz += Dsrc.Qd[qi * NV + k] * vzd[axis * A2 + qb * NV + k];
+    for (int k = 0; k < NV; ++k) qz += qdr[k] * vzd[axis * A2 + qb * NV + k];
   }
   project_reduce(false);
   if (prow) vw[axis * A2 + I] = T((lam - rhod * double(tr)) - qz);
@@ -1022,7 +1038,15 @@ __device__ __forceinline__ void fused_block(const Desc &D) {
       lds[L.qrows + e] = (k < NV && (bq == 0 || qcs)) ? T(D.Qd[i * NV + k]) : T(0);
     }
   }
-  for (int i = tid; i < 2 * TILE * L.wave_stride; i += blockDim.x) lds[L.wave0 + i] = T(0);
+  // (the reduction scratch at the end of each wave's area is written before
+  // it is read and is left as it is)
+  {
+    const int zero_len = wave_layout(NV, RED, int(sizeof(double) / sizeof(T))).red;
+    for (int i = tid; i < 2 * TILE * zero_len; i += blockDim.x) {
+      const int w = i / zero_len;
+      lds[L.wave0 + w * L.wave_stride + (i - w * zero_len)] = T(0);
+    }
+  }
   __syncthreads();
 
   // Every trajectory slot of the block runs the loop (it has block-wide
