@@ -500,8 +500,9 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
   // ---- xi3/xi4 projection of every (circle, obstacle, t), velocity and
   // acceleration, then the per-wave partial sums of F^T (F xi - g) (4
   // blocks of NP rows), exchanged between the two waves; afterwards lane
-  // (axis, I) of the position rows holds its row of the total in `tr`.  `rp` keeps this lane's heading
-  // residual psi_sign (psi - psi_hat) for the next heading step.
+  // (axis, I) of the position rows holds its row of the total in `tr`.
+  // `rp` keeps this lane's heading residual psi_sign (psi - psi_hat) for
+  // the next heading step.
   T tr = T(0), rp = T(0);
   // near-obstacle set of the last vote and the positions it was taken at
   T xvote = T(0), yvote = T(0), extvote = T(0);
@@ -560,8 +561,8 @@ __device__ void fused_body(const Desc &Dsrc, int l, bool live, int half, T *lds,
           rxl[i] = xl + rr[i] * ux;
           ryl[i] = yl + rr[i] * uy;
         }
-        // exact circle counts for m = C, C - 1 and C - 2 (every robot and
-        // uneven batch here), the tested form otherwise
+        // exact circle counts for m = C, C - 1 and C - 2 (robots of 3 to 5
+        // circles with C = 5), the tested form otherwise
         if (m == C) project_near(std::integral_constant<int, C>(), near_set);
         else if (C > 1 && m == C - 1) project_near(std::integral_constant<int, (C > 1 ? C - 1 : 0)>(), near_set);
         else if (C > 2 && m == C - 2) project_near(std::integral_constant<int, (C > 2 ? C - 2 : 0)>(), near_set);
