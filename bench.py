@@ -512,6 +512,41 @@ def error_vs_oracle(pb, gpu: dict, orc_state: dict):
             "within_1e-3": int((e <= 1e-3).sum())}
 
 
+def fixed_cost(workload: str = "c2", solves: int = 35):
+    """Time per fused solve with solves issued back to back (as the
+    benchmark's steps are) for K = 0, 1, 2 and the workload's K, without and
+    with the residual statistics: the difference between K and 0 is the
+    iterations' cost, the K = 0 time the set-up, first projection,
+    write-back and the gap between launches."""
+    import torch
+
+    from paper_2109_13030_amd import am, inputs
+    torch.cuda.set_device(0)
+    cfg = inputs.CONFIGS[workload]
+    pb, init = inputs.workload(workload)
+    h = am.Handle.for_problem(pb, "f32")
+    p = am.DeviceProblem(pb, "f32")
+    m, n, q = len(pb["r"]), len(pb["oa"]), pb["q"]
+    am.autotune(h, p, am.DeviceState(init, m, n, q, "f32"), cfg.iters)
+    rows = []
+    for res in (False, True):
+        for K in (0, 1, 2, cfg.iters):
+            sts = [am.DeviceState(init, m, n, q, "f32", residuals=res) for _ in range(solves + 5)]
+            for st in sts[:5]:
+                am.solve(h, p, st, K)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for st in sts[5:]:
+                am.solve(h, p, st, K)
+            e1.record()
+            torch.cuda.synchronize()
+            rows.append({"residuals": res, "K": K, "us_per_solve": e0.elapsed_time(e1) / solves * 1e3})
+            print(f"residuals={res} K={K}: {rows[-1]['us_per_solve']:.2f} us", file=sys.stderr, flush=True)
+    return {"workload": workload, "batch": int(init["cx"].shape[0]), "solves_back_to_back": solves,
+            "launch": {"tile": h.tile, "waves_per_simd": h.waves}, "rows": rows}
+
+
 def copy_by_size(launches=200):
     """Bandwidth of a plain elementwise copy (half the bytes read, half
     written) for the byte counts one launch of the plain path's elementwise
@@ -568,6 +603,9 @@ def main():
     ap.add_argument("--copy-ref", action="store_true",
                     help="run only a 512 MiB elementwise copy (y = x * 1), the size reference for "
                          "hardware byte counters, and exit")
+    ap.add_argument("--fixed-cost", action="store_true",
+                    help="run only the per-solve times of back-to-back fused solves for K = 0, 1, 2 and the "
+                         "workload's K, with and without residual statistics, and exit")
     ap.add_argument("--copy-sizes", action="store_true",
                     help="run only elementwise copies (y = x * 1) that move as many bytes as one launch of "
                          "the plain path's projection and target kernels at c2 and c4, and exit")
@@ -594,6 +632,9 @@ def main():
         return
     if args.copy_sizes:
         print(json.dumps(copy_by_size()), flush=True)
+        return
+    if args.fixed_cost:
+        print(json.dumps(fixed_cost(args.workload)), flush=True)
         return
     if args.uneven:
         print(json.dumps(run_uneven()), flush=True)
