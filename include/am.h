@@ -96,7 +96,7 @@ extern "C" {
 #define AM_RES_A_EXCESS   10  /* max_t |a| - amax                                */
 #define AM_RES_NONFINITE  11  /* 1 if any state value is NaN/Inf, else 0        */
 
-/* Limits of this build. */
+/* Size limits of the library (compile-time capacities of the kernels). */
 #define AM_MAX_Q       128    /* timesteps                                    */
 #define AM_MAX_CIRCLES 8
 #define AM_MAX_OBS     64
